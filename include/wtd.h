@@ -1,0 +1,146 @@
+/*
+ * wtd.h - C ABI of the MI355X (gfx950) Liouville-apply library for plane-wave,
+ * Gamma-point, Tamm-Dancoff hybrid TDDFT.
+ *
+ * The operator is L = D + K1e - K1d of the paper's Sec. 2.1 (Eqs. dterm,
+ * k1eterm, k1d and TDDFT_VEXX_TDA), acting on trial sets A = {a_v} of
+ * occupied-orbital-indexed functions (Eq. deltarho with B = 0), projected onto
+ * the unoccupied manifold (P_c, defined after Eq. k2dterm).  The eigenproblem
+ * is solved with the Davidson method named in Sec. 4.
+ *
+ * Conventions (Hartree atomic units, v_c = 1/|r - r'|):
+ *  - orthorhombic cell L0 x L1 x L2 bohr, Omega = L0 L1 L2; FFT grid n0 x n1 x n2;
+ *    a real-space field is stored as f[(i0*n1 + i1)*n2 + i2] (i2 fastest);
+ *  - G_m = 2 pi (m0/L0, m1/L1, m2/L2) for Miller indices m;
+ *  - a real orbital is phi(r) = Omega^-1/2 sum_{m in S} c(m) e^{i G_m.r} with
+ *    c(-m) = conj(c(m)); only the half sphere S+ is passed: m = 0 first, then
+ *    every m whose first nonzero component is positive.  Coefficient arrays
+ *    are [..][npw][2] (re, im); the imaginary part at m = 0 is ignored;
+ *  - inner product <f|g> = sum_{m in S+} w_m Re(conj f_m g_m), w_0 = 1, w_m = 2;
+ *  - the unoccupied manifold is the span of the supplied conduction orbitals
+ *    (P = sum_c |phi_c><phi_c|) and H_KS acts spectrally on occupied and
+ *    conduction orbitals, so D has entries eps_c - eps_v;
+ *  - the K1e term carries the spin factor c_K (2: closed-shell singlet; 0: the
+ *    spin-flip problem with exchange only, Eq. TDDFT_VEXX_TDA_SF with K1e,SF
+ *    dropped); f_xc is a real-space field;
+ *  - Coulomb kernel 4 pi/|G|^2 over the whole FFT box, value v_g0 at G = 0.
+ *
+ * All entry points return a wtd_status; negative values are errors (outputs
+ * undefined), positive values are warnings (outputs valid).  wtd_last_error()
+ * returns a thread-local message for the last failure.  No exception crosses
+ * the ABI.  One context is not thread-safe; distinct contexts are independent.
+ * Device pointers are HIP device memory on the device that was current when
+ * the context was created; every device operation is enqueued on the HIP
+ * stream given at creation.
+ */
+#ifndef WTD_H
+#define WTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wtd_ctx wtd_ctx;
+
+typedef enum {
+  WTD_OK = 0,
+  WTD_NOT_CONVERGED = 1,       /* warning: Davidson stopped at max_iter; outputs valid   */
+  WTD_ERR_ARG = -1,            /* null pointer, out-of-range scalar                     */
+  WTD_ERR_SHAPE = -2,          /* inconsistent sizes (grid vs sphere, nb > max_nb, ...)  */
+  WTD_ERR_OOM = -3,            /* device allocation failed or workspace cap exceeded    */
+  WTD_ERR_HIP = -4,            /* a HIP runtime call failed                             */
+  WTD_ERR_UNIMPLEMENTED = -5,  /* the requested operation is not provided              */
+  WTD_ERR_NONFINITE = -6       /* non-finite values detected (when checking is enabled) */
+} wtd_status;
+
+typedef enum { WTD_FP64 = 0, WTD_FP32 = 1 } wtd_precision;
+
+enum { WTD_TERM_D = 1, WTD_TERM_K1E = 2, WTD_TERM_K1D = 4, WTD_TERM_ALL = 7 };
+
+typedef struct {
+  int32_t n[3];            /* FFT grid; each n_i > 2 max|m_i| and n_i a product of 2,3,5   */
+  double cell[3];          /* orthorhombic edge lengths (bohr)                              */
+  int32_t npw;             /* number of half-sphere plane waves (m = 0 first)               */
+  const int32_t *mill;     /* host [npw][3] Miller indices                                  */
+  int32_t nocc, ncond;     /* occupied / conduction orbital counts                          */
+  const double *c_occ;     /* device [nocc][npw][2] FP64                                     */
+  const double *c_cond;    /* device [ncond][npw][2] FP64; orthonormal, orthogonal to c_occ */
+  const double *eps_occ;   /* host [nocc] Hartree                                           */
+  const double *eps_cond;  /* host [ncond] Hartree                                          */
+  const double *fxc;       /* device [n0*n1*n2] Ha bohr^3 (layout above); NULL means 0      */
+  double alpha;            /* exact-exchange fraction alpha_EXX                             */
+  double k1e_scale;        /* c_K                                                           */
+  double v_g0;             /* Coulomb kernel value at G = 0 (0 drops it)                    */
+  uint32_t term_mask;      /* WTD_TERM_* subset (WTD_TERM_ALL in production)                */
+  wtd_precision prec;      /* FP64, or FP32 bulk arithmetic (transforms, pair potentials,
+                              contraction, projections) with FP64 Davidson subspace work    */
+} wtd_system;
+
+/* Create a context.  Copies and converts every system array into context-owned
+ * device memory (the caller may free its arrays afterwards), transforms the
+ * occupied orbitals to real space and allocates the workspace for blocks of up
+ * to max_nb trial vectors.  hip_stream is a hipStream_t (NULL: null stream).
+ * Errors: WTD_ERR_ARG (null pointers, max_nb < 1, bad term mask / precision),
+ * WTD_ERR_SHAPE (grid too small for the sphere, unsupported grid factor,
+ * duplicate or out-of-half-space Miller indices, m = 0 not first),
+ * WTD_ERR_OOM, WTD_ERR_HIP.  On error *out is set to NULL.                      */
+wtd_status wtd_create(const wtd_system *sys, int32_t max_nb, void *hip_stream, wtd_ctx **out);
+
+/* Release every device and host resource of the context (NULL is accepted).    */
+wtd_status wtd_destroy(wtd_ctx *ctx);
+
+/* Replace the occupied orbitals (device [nocc][npw][2] FP64, same sphere) and
+ * re-transform them to real space.  Asynchronous on the context stream.        */
+wtd_status wtd_set_occ(wtd_ctx *ctx, const double *c_occ);
+
+/* la = P L P a for a block of nb trial sets (Eq. TDDFT_VEXX_TDA's left-hand
+ * side, the paper's Sec. 2.1 terms selected by term_mask).
+ * a, la: device [nb][nocc][npw][2] in the context precision (double or float);
+ * they must not alias.  Asynchronous on the context stream.
+ * Errors: WTD_ERR_ARG (null), WTD_ERR_SHAPE (nb < 1 or nb > max_nb).           */
+wtd_status wtd_apply_liouville(wtd_ctx *ctx, int32_t nb, const void *a, void *la);
+
+/* The same operator in transition coordinates, always FP64 at the boundary:
+ * T = Phi_c^T L Phi_c X, X and T device [nb][nocc][ncond] FP64.  This is the
+ * form the Davidson solver applies (Sec. 4).  Asynchronous.                     */
+wtd_status wtd_apply_transition(wtd_ctx *ctx, int32_t nb, const double *X, double *T);
+
+/* Gradients of E = sum Re(conj(g_la) la) with respect to the (re, im) parts of
+ * a and of the occupied coefficients.  Not provided by this version: returns
+ * WTD_ERR_UNIMPLEMENTED.                                                         */
+wtd_status wtd_apply_liouville_bwd(wtd_ctx *ctx, int32_t nb, const void *a, const void *g_la,
+                                   void *g_a, void *g_occ);
+
+/* Block Davidson for the nroots lowest eigenpairs of L (Sec. 4; normalisation
+ * sum_v <x_v|x_v> = 1 of Eq. ltda).  Synchronous.
+ * nb: block size (nroots <= nb <= max_nb); tol: residual 2-norm per root;
+ * max_sub: basis cap before restart (<= 0: 4*nb); guess: device
+ * [nb][nocc][npw][2] FP64 or NULL (lowest unit transitions).
+ * Outputs: omega, resid host [nroots] ascending; x device [nroots][nocc][npw][2]
+ * FP64 (may be NULL); n_iter host (may be NULL).
+ * Returns WTD_NOT_CONVERGED (a warning) if max_iter is reached.                  */
+wtd_status wtd_davidson(wtd_ctx *ctx, int32_t nroots, int32_t nb, double tol, int32_t max_iter,
+                        int32_t max_sub, const double *guess, double *omega, double *x,
+                        double *resid, int32_t *n_iter);
+
+/* Per-stage timing with HIP events on the context stream (for profiling).
+ * wtd_profile_enable(ctx, 1) starts recording; wtd_profile_read copies the
+ * accumulated milliseconds and call counts of up to n stages and their names
+ * (static strings) and resets them.  Returns the number of stages in *count.  */
+wtd_status wtd_profile_enable(wtd_ctx *ctx, int32_t on);
+wtd_status wtd_profile_read(wtd_ctx *ctx, int32_t n, double *ms, int64_t *calls,
+                            const char **names, int32_t *count);
+
+/* Device bytes held by the context (orbital fields, tables and workspace).      */
+wtd_status wtd_workspace_bytes(const wtd_ctx *ctx, size_t *bytes);
+
+const char *wtd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WTD_H */

@@ -1,0 +1,928 @@
+// C ABI, context set-up and the host-side schedule of the Liouville apply.
+//
+// Apply schedule for a block of nb trial sets (the paper's Sec. 2.1 terms; all
+// device work on the context stream):
+//   1. S = Phi_c^T a                        (MFMA GEMM, weighted Gamma inner product)
+//   2. a~ = Phi_c S                         (MFMA GEMM): projected input
+//   3. a~(r) and drho_b = sum_v phi_v a~_bv (stick + plane pass, fused reduction)
+//   4. v_H,b = v_c * drho_b                 (Poisson on density sticks)       [K1e]
+//   5. tau_vv' = v_c * (phi_v phi_v'), v <= v' (packed pair Poisson)          [K1d]
+//   6. R_bv = c_K phi_v (v_H,b + f_xc drho_b) - alpha sum_v' tau_vv' a~_bv'
+//   7. r_bv = sphere coefficients of R_bv   (plane + stick pass, unpacking)
+//   8. Q = Phi_c^T r ; T = (eps_c - eps_v) S + Q ; la = Phi_c T
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <set>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "wtd_internal.h"
+
+namespace wtd {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+// ---------------------------------------------------------------- device memory
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Profiler {
+  bool on = false;
+  static constexpr int kStages = 10;
+  const char* names[kStages] = {"project_in",     "trial_to_grid", "hartree",
+                                "pair_plane_fwd", "pair_stick_poisson", "pair_plane_inv",
+                                "contract",       "grid_to_sphere", "project_out",
+                                "davidson_small"};
+  double ms[kStages] = {};
+  int64_t calls[kStages] = {};
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> marks;  // (stage, index of start event)
+};
+
+}  // namespace
+
+}  // namespace wtd
+
+struct wtd_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  wtd_precision prec = WTD_FP64;
+  uint32_t mask = WTD_TERM_ALL;
+  int npw = 0, nocc = 0, nc = 0, max_nb = 0;
+  double alpha = 0, ck = 0, vg0 = 0;
+  wtd::Geometry g{};
+  std::vector<double> eps_occ_h, eps_cond_h;
+  std::vector<wtd::DevBuf> bufs;
+  size_t total_bytes = 0;
+  // device arrays (precision-typed as void*)
+  void* c_cond = nullptr;    // [nc][2 npw]
+  void* c_condw = nullptr;   // weighted copy for the Gamma inner product
+  void* c_occ = nullptr;     // [nocc][2 npw]
+  double* eps_occ = nullptr;
+  double* eps_cond = nullptr;
+  double* diag = nullptr;    // [nocc*nc] eps_c - eps_v (Davidson preconditioner)
+  void* fxc = nullptr;
+  void* phi = nullptr;       // [nocc][nr]
+  void* at = nullptr;        // [max_nb][nocc][nr]
+  void* R = nullptr;         // [max_nb][nocc][nr]
+  void* drho = nullptr;      // [max_nb][nr]
+  void* vh = nullptr;        // [max_nb][nr]
+  void* tau = nullptr;       // [npairs][nr]
+  void* wst = nullptr;       // [max packs][n0][nw] complex
+  void* dst = nullptr;       // [pair chunk][n0][nd] complex
+  void* ag = nullptr;        // [max_nb][nocc][2 npw]
+  void* rg = nullptr;        // [max_nb][nocc][2 npw]
+  void* S = nullptr;         // [max_nb*nocc][nc]
+  void* Q = nullptr;
+  void* Tm = nullptr;
+  int npairs = 0, npack_pairs = 0, pair_chunk = 0;
+  int4* quads = nullptr;     // pair packs
+  int4* hquads = nullptr;    // Hartree packs
+  int* pidx = nullptr;       // [nocc][nocc]
+  wtd::Profiler prof;
+};
+
+namespace wtd {
+
+namespace {
+
+void* dalloc(wtd_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw StatusError{WTD_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  c->bufs.push_back({p, bytes});
+  c->total_bytes += bytes;
+  return p;
+}
+
+void free_all(wtd_ctx* c) {
+  for (auto& b : c->bufs) (void)hipFree(b.p);
+  c->bufs.clear();
+  for (auto e : c->prof.pool) (void)hipEventDestroy(e);
+  c->prof.pool.clear();
+}
+
+// Host-to-device copy that has completed when it returns (the source may be a
+// temporary).
+void h2d(wtd_ctx* c, void* dst, const void* src, size_t bytes) {
+  WTD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  WTD_HIP(hipStreamSynchronize(c->stream));
+}
+
+template <typename T>
+void upload(wtd_ctx* c, void* dst, const std::vector<T>& h) {
+  h2d(c, dst, h.data(), h.size() * sizeof(T));
+}
+
+// ---------------------------------------------------------------- profiling
+void prof_mark(wtd_ctx* c, int stage) {
+  if (!c->prof.on) return;
+  Profiler& P = c->prof;
+  while (P.pool.size() < P.used + 2) {
+    hipEvent_t e;
+    WTD_HIP(hipEventCreate(&e));
+    P.pool.push_back(e);
+  }
+  WTD_HIP(hipEventRecord(P.pool[P.used], c->stream));
+  P.marks.push_back({stage, P.used});
+  P.used += 2;
+}
+
+void prof_end(wtd_ctx* c) {
+  if (!c->prof.on || c->prof.marks.empty()) return;
+  Profiler& P = c->prof;
+  WTD_HIP(hipEventRecord(P.pool[P.marks.back().second + 1], c->stream));
+}
+
+// Close the current stage and open the next one.
+void prof_next(wtd_ctx* c, int stage) {
+  if (!c->prof.on) return;
+  Profiler& P = c->prof;
+  if (!P.marks.empty()) {
+    const size_t idx = P.marks.back().second + 1;
+    WTD_HIP(hipEventRecord(P.pool[idx], c->stream));
+  }
+  prof_mark(c, stage);
+}
+
+void prof_collect(wtd_ctx* c) {
+  if (!c->prof.on) return;
+  Profiler& P = c->prof;
+  if (P.marks.empty()) return;
+  WTD_HIP(hipEventSynchronize(P.pool[P.marks.back().second + 1]));
+  for (auto& m : P.marks) {
+    float ms = 0.f;
+    WTD_HIP(hipEventElapsedTime(&ms, P.pool[m.second], P.pool[m.second + 1]));
+    P.ms[m.first] += ms;
+    P.calls[m.first] += 1;
+  }
+  P.marks.clear();
+  P.used = 0;
+}
+
+// ---------------------------------------------------------------- geometry
+FFTPlan make_plan(int n) {
+  FFTPlan P{};
+  P.n = n;
+  int rem = n, np = 0, prod = 1;
+  const int order[] = {8, 5, 4, 3, 2};
+  while (rem > 1) {
+    int r = 0;
+    for (int cand : order)
+      if (rem % cand == 0) {
+        r = cand;
+        break;
+      }
+    WTD_REQUIRE(r != 0, WTD_ERR_SHAPE,
+                "grid size " + std::to_string(n) + " is not a product of 2, 3 and 5");
+    WTD_REQUIRE(np < kMaxPasses, WTD_ERR_SHAPE, "too many FFT passes");
+    P.rad[np] = r;
+    P.p[np] = prod;
+    prod *= r;
+    rem /= r;
+    ++np;
+  }
+  P.np = np;
+  return P;
+}
+
+int fold(int m, int n) { return ((m % n) + n) % n; }
+int unfold(int k, int n) { return (2 * k < n) ? k : k - n; }
+
+template <typename T>
+void* make_twiddles(wtd_ctx* c, int n) {
+  std::vector<T> h(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)n;
+    h[2 * j] = (T)std::cos(a);
+    h[2 * j + 1] = (T)(-std::sin(a));
+  }
+  void* d = dalloc(c, h.size() * sizeof(T));
+  upload(c, d, h);
+  return d;
+}
+
+template <typename T>
+void build_geometry(wtd_ctx* c, const wtd_system* sys) {
+  Geometry& g = c->g;
+  g.n0 = sys->n[0];
+  g.n1 = sys->n[1];
+  g.n2 = sys->n[2];
+  g.plane = g.n1 * g.n2;
+  g.nr = (int64_t)g.n0 * g.plane;
+  g.omega = sys->cell[0] * sys->cell[1] * sys->cell[2];
+  g.plan0 = make_plan(g.n0);
+  g.plan1 = make_plan(g.n1);
+  g.plan2 = make_plan(g.n2);
+  g.tw0 = make_twiddles<T>(c, g.n0);
+  g.tw1 = make_twiddles<T>(c, g.n1);
+  g.tw2 = make_twiddles<T>(c, g.n2);
+  const int n[3] = {g.n0, g.n1, g.n2};
+  const double b[3] = {2 * M_PI / sys->cell[0], 2 * M_PI / sys->cell[1], 2 * M_PI / sys->cell[2]};
+
+  // validate the half sphere
+  const int npw = sys->npw;
+  const int32_t* mill = sys->mill;
+  WTD_REQUIRE(mill[0] == 0 && mill[1] == 0 && mill[2] == 0, WTD_ERR_SHAPE,
+              "the first Miller index must be m = 0");
+  std::set<std::tuple<int, int, int>> seen;
+  double g2max = 0.0;
+  for (int h = 0; h < npw; ++h) {
+    const int m0 = mill[3 * h], m1 = mill[3 * h + 1], m2 = mill[3 * h + 2];
+    for (int i = 0; i < 3; ++i)
+      WTD_REQUIRE(2 * std::abs(mill[3 * h + i]) < n[i], WTD_ERR_SHAPE,
+                  "grid too small for the plane-wave sphere (need n_i > 2 max|m_i|)");
+    if (h > 0) {
+      const int first = m0 != 0 ? m0 : (m1 != 0 ? m1 : m2);
+      WTD_REQUIRE(first > 0, WTD_ERR_SHAPE, "Miller index outside the Gamma half space");
+    }
+    WTD_REQUIRE(seen.insert({m0, m1, m2}).second, WTD_ERR_SHAPE, "duplicate Miller index");
+    const double g2 = (m0 * b[0]) * (m0 * b[0]) + (m1 * b[1]) * (m1 * b[1]) +
+                      (m2 * b[2]) * (m2 * b[2]);
+    g2max = std::max(g2max, g2);
+  }
+
+  // wave sticks: columns (k1, k2) holding +m or -m
+  std::map<int, int> wkey;
+  for (int h = 0; h < npw; ++h)
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const int k1 = fold(sg * mill[3 * h + 1], n[1]), k2 = fold(sg * mill[3 * h + 2], n[2]);
+      wkey[k1 * n[2] + k2] = 0;
+    }
+  std::vector<int> wk12;
+  for (auto& kv : wkey) {
+    kv.second = (int)wk12.size();
+    wk12.push_back(kv.first);
+  }
+  g.nw = (int)wk12.size();
+  g.nwtile = (g.nw + kStickTile - 1) / kStickTile;
+  std::vector<std::vector<int4>> tiles(g.nwtile);
+  std::vector<int> pos(2 * (size_t)npw);
+  for (int h = 0; h < npw; ++h) {
+    for (int sg = 1; sg >= -1; sg -= 2) {
+      if (h == 0 && sg < 0) {
+        pos[2 * h + 1] = pos[2 * h];
+        continue;
+      }
+      const int k0 = fold(sg * mill[3 * h], n[0]);
+      const int k1 = fold(sg * mill[3 * h + 1], n[1]), k2 = fold(sg * mill[3 * h + 2], n[2]);
+      const int s = wkey[k1 * n[2] + k2];
+      tiles[s / kStickTile].push_back(int4{h, sg, s % kStickTile, k0});
+      pos[2 * h + (sg > 0 ? 0 : 1)] = k0 * g.nw + s;
+    }
+  }
+  std::vector<int> off(g.nwtile + 1, 0);
+  std::vector<int4> ent;
+  for (int t = 0; t < g.nwtile; ++t) {
+    off[t] = (int)ent.size();
+    ent.insert(ent.end(), tiles[t].begin(), tiles[t].end());
+  }
+  off[g.nwtile] = (int)ent.size();
+  int* d_wk = (int*)dalloc(c, wk12.size() * sizeof(int));
+  upload(c, d_wk, wk12);
+  int* d_off = (int*)dalloc(c, off.size() * sizeof(int));
+  upload(c, d_off, off);
+  int4* d_ent = (int4*)dalloc(c, ent.size() * sizeof(int4));
+  h2d(c, d_ent, ent.data(), ent.size() * sizeof(int4));
+  int2* d_pos = (int2*)dalloc(c, pos.size() * sizeof(int));
+  upload(c, d_pos, pos);
+  g.wst_k12 = d_wk;
+  g.wtile_off = d_off;
+  g.wtile_ent = d_ent;
+  g.sph_pos = d_pos;
+
+  // density sticks: projections of |G| <= 2 max|G_sphere| (pair products), folded
+  std::set<int> dkey;
+  const int r1 = (int)std::floor(2.0 * std::sqrt(g2max) / b[1]) + 1;
+  const int r2 = (int)std::floor(2.0 * std::sqrt(g2max) / b[2]) + 1;
+  for (int m1 = -r1; m1 <= r1; ++m1)
+    for (int m2 = -r2; m2 <= r2; ++m2) {
+      const double gg = (m1 * b[1]) * (m1 * b[1]) + (m2 * b[2]) * (m2 * b[2]);
+      if (gg <= 4.0 * g2max * (1.0 + 1e-12)) dkey.insert(fold(m1, n[1]) * n[2] + fold(m2, n[2]));
+    }
+  std::vector<int> dk12(dkey.begin(), dkey.end());
+  g.nd = (int)dk12.size();
+  int* d_dk = (int*)dalloc(c, dk12.size() * sizeof(int));
+  upload(c, d_dk, dk12);
+  g.dst_k12 = d_dk;
+  std::vector<T> kern((size_t)g.nd * g.n0);
+  for (int s = 0; s < g.nd; ++s) {
+    const int m1 = unfold(dk12[s] / n[2], n[1]), m2 = unfold(dk12[s] % n[2], n[2]);
+    for (int k0 = 0; k0 < g.n0; ++k0) {
+      const int m0 = unfold(k0, n[0]);
+      const double gg = (m0 * b[0]) * (m0 * b[0]) + (m1 * b[1]) * (m1 * b[1]) +
+                        (m2 * b[2]) * (m2 * b[2]);
+      const double v = gg > 0.0 ? 4.0 * M_PI / gg : c->vg0;
+      kern[(size_t)s * g.n0 + k0] = (T)(v / (double)g.nr);
+    }
+  }
+  void* d_kern = dalloc(c, kern.size() * sizeof(T));
+  upload(c, d_kern, kern);
+  g.dkern = d_kern;
+}
+
+// ---------------------------------------------------------------- context set-up
+template <typename T>
+void create_impl(wtd_ctx* c, const wtd_system* sys) {
+  build_geometry<T>(c, sys);
+  const int npw = c->npw, nocc = c->nocc, nc = c->nc, mnb = c->max_nb;
+  const int64_t nr = c->g.nr;
+  const size_t K = 2 * (size_t)npw;
+  hipStream_t s = c->stream;
+
+  // orbitals in the working precision; weighted conduction copy for <phi_c|.>
+  c->c_occ = dalloc(c, (size_t)nocc * K * sizeof(T));
+  c->c_cond = dalloc(c, (size_t)nc * K * sizeof(T));
+  c->c_condw = dalloc(c, (size_t)nc * K * sizeof(T));
+  {
+    std::vector<double> hc((size_t)nc * K);
+    WTD_HIP(hipMemcpyAsync(hc.data(), sys->c_cond, hc.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipStreamSynchronize(s));
+    std::vector<T> a(hc.size()), w(hc.size());
+    for (int ci = 0; ci < nc; ++ci)
+      for (int h = 0; h < npw; ++h) {
+        const size_t i = (size_t)ci * K + 2 * h;
+        a[i] = (T)hc[i];
+        a[i + 1] = (h == 0) ? T(0) : (T)hc[i + 1];
+        const double wt = (h == 0) ? 1.0 : 2.0;
+        w[i] = (T)(wt * hc[i]);
+        w[i + 1] = (h == 0) ? T(0) : (T)(wt * hc[i + 1]);
+      }
+    upload(c, c->c_cond, a);
+    upload(c, c->c_condw, w);
+    WTD_HIP(hipStreamSynchronize(s));
+  }
+  c->eps_occ = (double*)dalloc(c, nocc * sizeof(double));
+  c->eps_cond = (double*)dalloc(c, nc * sizeof(double));
+  upload(c, c->eps_occ, c->eps_occ_h);
+  upload(c, c->eps_cond, c->eps_cond_h);
+  {
+    std::vector<double> d((size_t)nocc * nc);
+    for (int v = 0; v < nocc; ++v)
+      for (int ci = 0; ci < nc; ++ci) d[(size_t)v * nc + ci] = c->eps_cond_h[ci] - c->eps_occ_h[v];
+    c->diag = (double*)dalloc(c, d.size() * sizeof(double));
+    upload(c, c->diag, d);
+  }
+  c->fxc = dalloc(c, nr * sizeof(T));
+  if (sys->fxc) {
+    if (sizeof(T) == sizeof(double))
+      WTD_HIP(hipMemcpyAsync(c->fxc, sys->fxc, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else
+      launch_convert<double, float>(sys->fxc, (float*)c->fxc, nr, s);
+  } else {
+    WTD_HIP(hipMemsetAsync(c->fxc, 0, nr * sizeof(T), s));
+  }
+
+  // pairs v <= v' (row-major), packed two per complex transform
+  c->npairs = nocc * (nocc + 1) / 2;
+  c->npack_pairs = (c->npairs + 1) / 2;
+  {
+    std::vector<int2> pr;
+    std::vector<int> pidx((size_t)nocc * nocc);
+    for (int v = 0; v < nocc; ++v)
+      for (int w = v; w < nocc; ++w) {
+        pidx[(size_t)v * nocc + w] = pidx[(size_t)w * nocc + v] = (int)pr.size();
+        pr.push_back(int2{v, w});
+      }
+    std::vector<int4> q(c->npack_pairs);
+    for (int p = 0; p < c->npack_pairs; ++p) {
+      const int2 a = pr[2 * p];
+      const int2 b = (2 * p + 1 < c->npairs) ? pr[2 * p + 1] : int2{-1, -1};
+      q[p] = int4{a.x, a.y, b.x, b.y};
+    }
+    c->quads = (int4*)dalloc(c, q.size() * sizeof(int4));
+    h2d(c, c->quads, q.data(), q.size() * sizeof(int4));
+    c->pidx = (int*)dalloc(c, pidx.size() * sizeof(int));
+    upload(c, c->pidx, pidx);
+    std::vector<int4> hq((mnb + 1) / 2);
+    for (int p = 0; p < (int)hq.size(); ++p)
+      hq[p] = int4{2 * p, -1, (2 * p + 1 < mnb) ? 2 * p + 1 : -1, -1};
+    c->hquads = (int4*)dalloc(c, hq.size() * sizeof(int4));
+    h2d(c, c->hquads, hq.data(), hq.size() * sizeof(int4));
+    WTD_HIP(hipStreamSynchronize(s));
+  }
+
+  // workspace
+  const int npt = (nocc + 1) / 2;
+  const size_t nwp = (size_t)std::max(mnb * npt, npt);
+  c->phi = dalloc(c, (size_t)nocc * nr * sizeof(T));
+  c->at = dalloc(c, (size_t)mnb * nocc * nr * sizeof(T));
+  c->R = dalloc(c, (size_t)mnb * nocc * nr * sizeof(T));
+  c->drho = dalloc(c, (size_t)mnb * nr * sizeof(T));
+  c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
+  if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D)) c->tau = dalloc(c, (size_t)c->npairs * nr * sizeof(T));
+  c->wst = dalloc(c, nwp * c->g.n0 * c->g.nw * sizeof(cplx<T>));
+  c->pair_chunk = std::max(1, std::min(c->npack_pairs, 512));
+  const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
+  c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nd * sizeof(cplx<T>));
+  c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
+  c->rg = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
+  c->S = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
+  c->Q = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
+  c->Tm = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
+}
+
+template <typename T>
+void transform_occ(wtd_ctx* c, const double* c_occ) {
+  const int nocc = c->nocc, npw = c->npw;
+  const size_t K = 2 * (size_t)npw;
+  hipStream_t s = c->stream;
+  if (sizeof(T) == sizeof(double))
+    WTD_HIP(hipMemcpyAsync(c->c_occ, c_occ, (size_t)nocc * K * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  else
+    launch_convert<double, float>(c_occ, (float*)c->c_occ, (int64_t)nocc * K, s);
+  launch_sphere_to_wsticks<T>(c->g, (const T*)c->c_occ, nocc, npw, 1, nocc, (cplx<T>*)c->wst, s);
+  launch_wsticks_to_fields<T>(c->g, (const cplx<T>*)c->wst, 1, nocc, nocc,
+                              (T)(1.0 / std::sqrt(c->g.omega)), (T*)c->phi, nullptr, nullptr, s);
+}
+
+// ---------------------------------------------------------------- the apply (steps 3-7)
+// Input: S [nb*nocc][nc] and a~ in G space (ag); output Q [nb*nocc][nc].
+template <typename T>
+void apply_core(wtd_ctx* c, int nb) {
+  const Geometry& g = c->g;
+  hipStream_t s = c->stream;
+  const int nocc = c->nocc, npw = c->npw, nc = c->nc;
+  const int K = 2 * npw;
+  const bool k1e = (c->mask & WTD_TERM_K1E) && c->ck != 0.0;
+  const bool k1d = (c->mask & WTD_TERM_K1D) && c->alpha != 0.0;
+  const int F = nb * nocc;
+  if (!k1e && !k1d) {
+    WTD_HIP(hipMemsetAsync(c->Q, 0, (size_t)F * nc * sizeof(T), s));
+    return;
+  }
+  const int npt = (nocc + 1) / 2;
+  // 3. trial transform (+ density response)
+  prof_next(c, 1);
+  launch_sphere_to_wsticks<T>(g, (const T*)c->ag, F, npw, nb, nocc, (cplx<T>*)c->wst, s);
+  launch_wsticks_to_fields<T>(g, (const cplx<T>*)c->wst, nb, nocc, nocc,
+                              (T)(1.0 / std::sqrt(g.omega)), (T*)c->at, (const T*)c->phi,
+                              k1e ? (T*)c->drho : nullptr, s);
+  // 4. Hartree potential of drho_b
+  if (k1e) {
+    prof_next(c, 2);
+    const int nh = (nb + 1) / 2;
+    launch_pairs_to_dsticks<T>(g, (const T*)c->drho, c->hquads, nh, nb, (cplx<T>*)c->dst, s);
+    launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, nh, s);
+    launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, nh, nb, (T*)c->vh, s);
+  }
+  // 5. pair potentials, in chunks of packed pairs
+  if (k1d) {
+    for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
+      const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
+      const int nf = std::min(2 * np, c->npairs - 2 * p0);
+      prof_next(c, 3);
+      launch_pairs_to_dsticks<T>(g, (const T*)c->phi, c->quads + p0, np, c->nocc,
+                                 (cplx<T>*)c->dst, s);
+      prof_next(c, 4);
+      launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
+      prof_next(c, 5);
+      launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
+                                  (T*)c->tau + (int64_t)2 * p0 * g.nr, s);
+    }
+  }
+  // 6. R
+  prof_next(c, 6);
+  launch_contract<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau, c->pidx,
+                     (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
+                     (T)c->alpha, k1e, k1d, (T*)c->R, s);
+  // 7. back to the sphere
+  prof_next(c, 7);
+  launch_fields_to_wsticks<T>(g, (const T*)c->R, nb, nocc, nocc, (cplx<T>*)c->wst, s);
+  launch_wsticks_to_sphere<T>(g, (cplx<T>*)c->wst, nb * npt, s);
+  launch_extract_sphere<T>(g, (const cplx<T>*)c->wst, nb, nocc, nocc, npw,
+                           (T)(std::sqrt(g.omega) / (double)g.nr), (T*)c->rg, s);
+  // 8a. Q = Phi_c^T r
+  prof_next(c, 8);
+  launch_gemm<T, true>(F, nc, K, (const T*)c->rg, K, (const T*)c->c_condw, K, (T*)c->Q, nc, s);
+}
+
+template <typename T>
+void apply_impl(wtd_ctx* c, int nb, const T* a, T* la) {
+  hipStream_t s = c->stream;
+  const int nocc = c->nocc, npw = c->npw, nc = c->nc;
+  const int K = 2 * npw, F = nb * nocc;
+  prof_mark(c, 0);
+  launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s);
+  launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
+  apply_core<T>(c, nb);
+  prof_next(c, 8);
+  launch_dterm_combine<T>(nb, nocc, nc, (const T*)c->S, (const T*)c->Q, c->eps_occ, c->eps_cond,
+                          (c->mask & WTD_TERM_D) != 0, (T*)c->Tm, s);
+  launch_gemm<T, false>(F, K, nc, (const T*)c->Tm, nc, (const T*)c->c_cond, K, la, K, s);
+  prof_end(c);
+  prof_collect(c);
+}
+
+template <typename T>
+void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout) {
+  hipStream_t s = c->stream;
+  const int nocc = c->nocc, npw = c->npw, nc = c->nc;
+  const int K = 2 * npw, F = nb * nocc;
+  prof_mark(c, 0);
+  if (sizeof(T) == sizeof(double))
+    WTD_HIP(hipMemcpyAsync(c->S, X, (size_t)F * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else
+    launch_convert<double, float>(X, (float*)c->S, (int64_t)F * nc, s);
+  launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
+  apply_core<T>(c, nb);
+  prof_next(c, 8);
+  launch_transition_out(nb, nocc, nc, c->Q, sizeof(T) == sizeof(float), X, c->eps_occ,
+                        c->eps_cond, (c->mask & WTD_TERM_D) != 0, Tout, s);
+  prof_end(c);
+  prof_collect(c);
+}
+
+void apply_transition_any(wtd_ctx* c, int nb, const double* X, double* T) {
+  if (c->prec == WTD_FP64)
+    apply_transition_impl<double>(c, nb, X, T);
+  else
+    apply_transition_impl<float>(c, nb, X, T);
+}
+
+// ---------------------------------------------------------------- Davidson (FP64)
+struct DavWork {
+  wtd_ctx* c;
+  std::vector<void*> mem;
+  ~DavWork() {
+    for (void* p : mem) (void)hipFree(p);
+  }
+  double* alloc(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 2) * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw StatusError{WTD_ERR_OOM, "Davidson workspace allocation failed"};
+    }
+    mem.push_back(p);
+    return (double*)p;
+  }
+};
+
+wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_iter, int max_sub,
+                         const double* guess, double* omega, double* x, double* resid,
+                         int32_t* n_iter) {
+  hipStream_t s = c->stream;
+  const int nocc = c->nocc, nc = c->nc, npw = c->npw;
+  const int64_t n = (int64_t)nocc * nc;
+  nb = (int)std::min<int64_t>(nb, n);
+  if (max_sub <= 0) max_sub = 4 * nb;
+  max_sub = std::max(max_sub, 2 * nb);
+  max_sub = (int)std::min<int64_t>(max_sub, n);
+  WTD_REQUIRE(max_sub <= 256, WTD_ERR_SHAPE, "max_sub must not exceed 256");
+  DavWork w{c, {}};
+  double* V = w.alloc((size_t)max_sub * n);
+  double* W = w.alloc((size_t)max_sub * n);
+  double* H = w.alloc((size_t)max_sub * max_sub);
+  double* evals = w.alloc(max_sub);
+  double* evecs = w.alloc(2 * (size_t)max_sub * max_sub);
+  double* Xr = w.alloc((size_t)nb * n);
+  double* WY = w.alloc((size_t)nb * n);
+  double* Rr = w.alloc((size_t)nb * n);
+  double* Tc = w.alloc((size_t)nb * n);
+  double* rn2 = w.alloc(nb);
+  double* coef = w.alloc(max_sub);
+  int* active = (int*)w.alloc(nb);
+
+  // guess
+  int m = 0;
+  if (guess) {
+    // project the G-space guess onto transition coordinates: X = Phi_c^T g
+    std::vector<double> gx((size_t)nb * n);
+    double* Sx = w.alloc((size_t)nb * n);
+    double* Cw = w.alloc((size_t)nc * 2 * npw);
+    if (c->prec == WTD_FP64) {
+      launch_gemm<double, true>(nb * nocc, nc, 2 * npw, guess, 2 * npw, (const double*)c->c_condw,
+                                2 * npw, Sx, nc, s);
+    } else {
+      launch_convert<float, double>((const float*)c->c_condw, Cw, (int64_t)nc * 2 * npw, s);
+      launch_gemm<double, true>(nb * nocc, nc, 2 * npw, guess, 2 * npw, Cw, 2 * npw, Sx, nc, s);
+    }
+    WTD_HIP(hipMemcpyAsync(Tc, Sx, (size_t)nb * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<int> idx(n);
+    for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+      const int va = a / nc, ca = a % nc, vb = b / nc, cb = b % nc;
+      const double da = c->eps_cond_h[ca] - c->eps_occ_h[va];
+      const double db = c->eps_cond_h[cb] - c->eps_occ_h[vb];
+      if (da != db) return da < db;
+      if (ca != cb) return ca < cb;
+      return va > vb;
+    });
+    std::vector<double> g((size_t)nb * n, 0.0);
+    for (int j = 0; j < nb; ++j) g[(size_t)j * n + idx[j]] = 1.0;
+    h2d(c, Tc, g.data(), g.size() * sizeof(double));
+  }
+
+  std::vector<double> h_norm(nb), h_th(max_sub), h_rn(nb);
+  // orthonormalise a block of k candidate rows (at Tc) against V[0..m) and each other,
+  // appending accepted rows to V; returns the number appended.
+  auto orthonormalise_append = [&](int k) -> int {
+    int added = 0;
+    for (int j = 0; j < k; ++j) {
+      double* t = Tc + (int64_t)j * n;
+      for (int pass = 0; pass < 2; ++pass) {
+        if (m + added > 0) {
+          launch_gram(V, m + added, t, 1, n, coef, 1, s);
+          launch_axpy_cols(t, V, coef, m + added, 1, n, s);
+        }
+      }
+      launch_col_norms(t, 1, n, rn2, s);
+      double nrm2 = 0.0;
+      WTD_HIP(hipMemcpyAsync(&nrm2, rn2, sizeof(double), hipMemcpyDeviceToHost, s));
+      WTD_HIP(hipStreamSynchronize(s));
+      const double nrm = std::sqrt(nrm2);
+      if (!(nrm >= 1e-10)) continue;
+      launch_scale_rows(t, 1.0 / nrm, n, s);
+      WTD_HIP(hipMemcpyAsync(V + (int64_t)(m + added) * n, t, n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+      ++added;
+    }
+    return added;
+  };
+
+  int added = orthonormalise_append(nb);
+  WTD_REQUIRE(added > 0, WTD_ERR_ARG, "Davidson guess block is rank deficient");
+  apply_transition_any(c, added, V, W);
+  m = added;
+  int it = 0;
+  bool converged = false;
+  int kcur = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    launch_gram(V, m, W, m, n, H, max_sub, s);
+    launch_jacobi_eig(H, m, max_sub, evals, evecs, s);
+    const int k = std::min(nb, m);
+    kcur = k;
+    launch_lincomb(V, m, n, evecs, m, k, Xr, s);
+    launch_lincomb(W, m, n, evecs, m, k, WY, s);
+    launch_residual(WY, Xr, evals, k, n, Rr, rn2, s);
+    WTD_HIP(hipMemcpyAsync(h_th.data(), evals, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipMemcpyAsync(h_rn.data(), rn2, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) h_rn[j] = std::sqrt(std::max(h_rn[j], 0.0));
+    converged = true;
+    for (int j = 0; j < std::min(nroots, k); ++j)
+      if (!(h_rn[j] <= tol)) converged = false;
+    if (!std::isfinite(h_th[0])) throw StatusError{WTD_ERR_NONFINITE, "non-finite Ritz value"};
+    if (converged) break;
+    std::vector<int> act;
+    for (int j = 0; j < k; ++j)
+      if (h_rn[j] > tol) act.push_back(j);
+    h2d(c, active, act.data(), act.size() * sizeof(int));
+    launch_precondition(Rr, evals, c->diag, (int)act.size(), n, active, Tc, s);
+    if (m + (int)act.size() > max_sub) {
+      // restart from the current Ritz vectors
+      WTD_HIP(hipMemcpyAsync(V, Xr, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      WTD_HIP(hipMemcpyAsync(W, WY, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      m = k;
+    }
+    const int na = orthonormalise_append((int)act.size());
+    if (na == 0) break;
+    apply_transition_any(c, na, V + (int64_t)m * n, W + (int64_t)m * n);
+    m += na;
+  }
+  const int nr_out = std::min(nroots, kcur);
+  for (int j = 0; j < nroots; ++j) {
+    omega[j] = j < nr_out ? h_th[j] : NAN;
+    if (resid) resid[j] = j < nr_out ? h_rn[j] : NAN;
+  }
+  if (n_iter) *n_iter = std::min(it, max_iter);
+  if (x) {
+    // x_k = Phi_c X_k in G space (FP64)
+    const int K = 2 * npw;
+    if (c->prec == WTD_FP64) {
+      launch_gemm<double, false>(nr_out * nocc, K, nc, Xr, nc, (const double*)c->c_cond, K, x, K,
+                                 s);
+    } else {
+      double* Cd = w.alloc((size_t)nc * K);
+      launch_convert<float, double>((const float*)c->c_cond, Cd, (int64_t)nc * K, s);
+      launch_gemm<double, false>(nr_out * nocc, K, nc, Xr, nc, Cd, K, x, K, s);
+    }
+  }
+  WTD_HIP(hipStreamSynchronize(s));
+  return converged ? WTD_OK : WTD_NOT_CONVERGED;
+}
+
+template <typename F>
+wtd_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const StatusError& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return WTD_ERR_OOM;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return WTD_ERR_HIP;
+  }
+}
+
+}  // namespace
+}  // namespace wtd
+
+using namespace wtd;
+
+extern "C" {
+
+const char* wtd_last_error(void) { return g_last_error.c_str(); }
+
+wtd_status wtd_create(const wtd_system* sys, int32_t max_nb, void* hip_stream, wtd_ctx** out) {
+  if (out) *out = nullptr;
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(sys && out, WTD_ERR_ARG, "null system or output pointer");
+    WTD_REQUIRE(sys->mill && sys->c_occ && sys->c_cond && sys->eps_occ && sys->eps_cond,
+                WTD_ERR_ARG, "null array in wtd_system");
+    WTD_REQUIRE(max_nb >= 1, WTD_ERR_ARG, "max_nb must be >= 1");
+    WTD_REQUIRE(sys->npw >= 1 && sys->nocc >= 1 && sys->ncond >= 1, WTD_ERR_SHAPE,
+                "npw, nocc and ncond must be positive");
+    WTD_REQUIRE(sys->n[0] >= 2 && sys->n[1] >= 2 && sys->n[2] >= 2, WTD_ERR_SHAPE, "grid too small");
+    WTD_REQUIRE(sys->cell[0] > 0 && sys->cell[1] > 0 && sys->cell[2] > 0, WTD_ERR_ARG,
+                "cell lengths must be positive");
+    WTD_REQUIRE(sys->prec == WTD_FP64 || sys->prec == WTD_FP32, WTD_ERR_ARG, "bad precision");
+    WTD_REQUIRE((sys->term_mask & ~7u) == 0, WTD_ERR_ARG, "bad term mask");
+    WTD_REQUIRE(std::isfinite(sys->alpha) && std::isfinite(sys->k1e_scale) &&
+                    std::isfinite(sys->v_g0),
+                WTD_ERR_ARG, "non-finite scalar parameter");
+    std::unique_ptr<wtd_ctx> c(new wtd_ctx());
+    c->stream = (hipStream_t)hip_stream;
+    WTD_HIP(hipGetDevice(&c->device));
+    c->prec = sys->prec;
+    c->mask = sys->term_mask;
+    c->npw = sys->npw;
+    c->nocc = sys->nocc;
+    c->nc = sys->ncond;
+    c->max_nb = max_nb;
+    c->alpha = sys->alpha;
+    c->ck = sys->k1e_scale;
+    c->vg0 = sys->v_g0;
+    c->eps_occ_h.assign(sys->eps_occ, sys->eps_occ + sys->nocc);
+    c->eps_cond_h.assign(sys->eps_cond, sys->eps_cond + sys->ncond);
+    try {
+      if (c->prec == WTD_FP64) {
+        create_impl<double>(c.get(), sys);
+        transform_occ<double>(c.get(), sys->c_occ);
+      } else {
+        create_impl<float>(c.get(), sys);
+        transform_occ<float>(c.get(), sys->c_occ);
+      }
+      WTD_HIP(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      free_all(c.get());
+      throw;
+    }
+    *out = c.release();
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_destroy(wtd_ctx* ctx) {
+  if (!ctx) return WTD_OK;
+  return guarded([&]() -> wtd_status {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_set_occ(wtd_ctx* ctx, const double* c_occ) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && c_occ, WTD_ERR_ARG, "null argument");
+    if (ctx->prec == WTD_FP64)
+      transform_occ<double>(ctx, c_occ);
+    else
+      transform_occ<float>(ctx, c_occ);
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_apply_liouville(wtd_ctx* ctx, int32_t nb, const void* a, void* la) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && a && la, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
+    WTD_REQUIRE(a != la, WTD_ERR_ARG, "a and la must not alias");
+    if (ctx->prec == WTD_FP64)
+      apply_impl<double>(ctx, nb, (const double*)a, (double*)la);
+    else
+      apply_impl<float>(ctx, nb, (const float*)a, (float*)la);
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_apply_transition(wtd_ctx* ctx, int32_t nb, const double* X, double* T) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && X && T, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
+    WTD_REQUIRE((const void*)X != (void*)T, WTD_ERR_ARG, "X and T must not alias");
+    apply_transition_any(ctx, nb, X, T);
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_apply_liouville_bwd(wtd_ctx* ctx, int32_t nb, const void* a, const void* g_la,
+                                   void* g_a, void* g_occ) {
+  (void)nb;
+  (void)a;
+  (void)g_la;
+  (void)g_a;
+  (void)g_occ;
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    throw StatusError{WTD_ERR_UNIMPLEMENTED, "wtd_apply_liouville_bwd is not provided yet"};
+  });
+}
+
+wtd_status wtd_davidson(wtd_ctx* ctx, int32_t nroots, int32_t nb, double tol, int32_t max_iter,
+                        int32_t max_sub, const double* guess, double* omega, double* x,
+                        double* resid, int32_t* n_iter) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && omega, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nroots >= 1 && nb >= nroots && nb <= ctx->max_nb, WTD_ERR_SHAPE,
+                "need 1 <= nroots <= nb <= max_nb");
+    WTD_REQUIRE(max_iter >= 1 && tol > 0.0, WTD_ERR_ARG, "need max_iter >= 1 and tol > 0");
+    return davidson_impl(ctx, nroots, nb, tol, max_iter, max_sub, guess, omega, x, resid,
+                         n_iter);
+  });
+}
+
+wtd_status wtd_profile_enable(wtd_ctx* ctx, int32_t on) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    ctx->prof.on = on != 0;
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_profile_read(wtd_ctx* ctx, int32_t n, double* ms, int64_t* calls,
+                            const char** names, int32_t* count) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    Profiler& P = ctx->prof;
+    for (int i = 0; i < std::min<int>(n, Profiler::kStages); ++i) {
+      if (ms) ms[i] = P.ms[i];
+      if (calls) calls[i] = P.calls[i];
+      if (names) names[i] = P.names[i];
+      P.ms[i] = 0.0;
+      P.calls[i] = 0;
+    }
+    if (count) *count = Profiler::kStages;
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_workspace_bytes(const wtd_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) {
+    set_error("null argument");
+    return WTD_ERR_ARG;
+  }
+  *bytes = ctx->total_bytes;
+  return WTD_OK;
+}
+
+}  // extern "C"
+
+#include "../../include/wtd_debug.h"
+
+extern "C" wtd_status wtd_debug_gemm(wtd_precision prec, int32_t m, int32_t n, int32_t k,
+                                     const void* a, int32_t lda, const void* b, int32_t ldb,
+                                     int32_t b_kmajor, void* c, int32_t ldc, void* hip_stream) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(a && b && c && m >= 0 && n >= 0 && k >= 0, WTD_ERR_ARG, "bad GEMM arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (prec == WTD_FP64) {
+      if (b_kmajor)
+        launch_gemm<double, true>(m, n, k, (const double*)a, lda, (const double*)b, ldb,
+                                  (double*)c, ldc, s);
+      else
+        launch_gemm<double, false>(m, n, k, (const double*)a, lda, (const double*)b, ldb,
+                                   (double*)c, ldc, s);
+    } else {
+      if (b_kmajor)
+        launch_gemm<float, true>(m, n, k, (const float*)a, lda, (const float*)b, ldb, (float*)c,
+                                 ldc, s);
+      else
+        launch_gemm<float, false>(m, n, k, (const float*)a, lda, (const float*)b, ldb, (float*)c,
+                                  ldc, s);
+    }
+    return WTD_OK;
+  });
+}

@@ -1,0 +1,122 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wtd.h"
+#include "wtd_fft.h"
+
+namespace wtd {
+
+void set_error(const std::string& msg);
+
+struct StatusError {
+  wtd_status code;
+  std::string msg;
+};
+
+#define WTD_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::wtd::StatusError{WTD_ERR_HIP, std::string(#call) + ": " +                \
+                                                hipGetErrorString(e_)};                \
+  } while (0)
+
+#define WTD_REQUIRE(cond, code, msg)                                \
+  do {                                                              \
+    if (!(cond)) throw ::wtd::StatusError{(code), std::string(msg)}; \
+  } while (0)
+
+// ----------------------------------------------------------------------------
+// Transform geometry shared by every kernel of one context.
+struct Geometry {
+  int n0, n1, n2;
+  int64_t nr;      // n0*n1*n2
+  int plane;       // n1*n2
+  double omega;
+  FFTPlan plan0, plan1, plan2;
+  // twiddle tables (one per axis), device, working precision
+  const void* tw0;
+  const void* tw1;
+  const void* tw2;
+  // wave sticks: columns along i0 of the wave-function sphere
+  int nw;                 // number of wave sticks
+  const int* wst_k12;     // [nw] k1*n2 + k2
+  int nwtile;             // stick tiles for the sphere->stick scatter
+  const int* wtile_off;   // [nwtile+1] CSR offsets into wtile_ent
+  const int4* wtile_ent;  // entries (h, sign, local stick, k0)
+  const int2* sph_pos;    // [npw] (stick*n0 + k0) of +m and of -m
+  // density sticks: columns that pair products can occupy
+  int nd;
+  const int* dst_k12;     // [nd]
+  const void* dkern;      // [nd][n0] Coulomb kernel / N_r, working precision
+};
+
+constexpr int kStickTile = 16;
+
+// ----------------------------------------------------------------------------
+// Kernel launchers (wtd_transforms.hip)
+template <typename T>
+void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
+                              int per_trial, cplx<T>* wst, hipStream_t s);
+template <typename T>
+void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
+                              int nfield_per_trial, T scale, T* out, const T* phi,
+                              T* drho, hipStream_t s);
+template <typename T>
+void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads, int npack,
+                             int limit, cplx<T>* dst, hipStream_t s);
+template <typename T>
+void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s);
+template <typename T>
+void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, int nfield,
+                              T* out, hipStream_t s);
+template <typename T>
+void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int per_trial,
+                              int nfield_per_trial, cplx<T>* wst, hipStream_t s);
+template <typename T>
+void launch_wsticks_to_sphere(const Geometry& g, cplx<T>* wst, int npack, hipStream_t s);
+template <typename T>
+void launch_extract_sphere(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
+                           int nfield_per_trial, int npw, T scale, T* coef, hipStream_t s);
+template <typename T>
+void launch_contract(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
+                     const T* tau, const int* pair_index, const T* vh, const T* drho,
+                     const T* fxc, T ck, T alpha, bool k1e, bool k1d, T* R, hipStream_t s);
+
+// GEMMs (wtd_gemm.hip).  C[m][n] = sum_k A[m*lda + k] * B(k, n), with
+// B(k, n) = B[n*ldb + k] (B_KMAJOR) or B[k*ldb + n].
+template <typename T, bool B_KMAJOR>
+void launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                 hipStream_t s);
+
+// Small elementwise kernels (wtd_transforms.hip)
+template <typename T>
+void launch_dterm_combine(int nb, int nocc, int nc, const T* S, const T* Q, const double* eps_occ,
+                          const double* eps_cond, bool with_d, T* out, hipStream_t s);
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s);
+void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_float,
+                           const double* X, const double* eps_occ, const double* eps_cond,
+                           bool with_d, double* T, hipStream_t s);
+
+// Davidson helpers (wtd_davidson.hip), FP64
+void launch_gram(const double* A, int na, const double* B, int nbv, int64_t n, double* out,
+                 int ldo, hipStream_t s);
+void launch_lincomb(const double* V, int m, int64_t n, const double* Y, int ldy, int k,
+                    double* out, hipStream_t s);
+void launch_residual(const double* WY, const double* X, const double* theta, int k, int64_t n,
+                     double* R, double* rnorm2, hipStream_t s);
+void launch_precondition(const double* R, const double* theta, const double* diag, int k,
+                         int64_t n, const int* active, double* T, hipStream_t s);
+void launch_jacobi_eig(double* H, int m, int ld, double* evals, double* evecs, hipStream_t s);
+void launch_axpy_cols(double* t, const double* V, const double* coef, int m, int k, int64_t n,
+                      hipStream_t s);
+void launch_col_norms(const double* t, int k, int64_t n, double* out, hipStream_t s);
+void launch_scale_rows(double* t, double f, int64_t n, hipStream_t s);
+
+}  // namespace wtd

@@ -1,0 +1,677 @@
+// Transforms between the plane-wave sphere and the real-space grid, the
+// pair-density Poisson solves and the exchange contraction.
+//
+// Paper mapping (Sec. 2.1 and Sec. 3.2):
+//  * sphere <-> real space: the orbital and trial-vector FFTs;
+//  * pairs_to_dsticks + dstick_poisson + dsticks_to_fields: the pair potentials
+//    tau_vv' = v_c * (phi_v phi_v') of Eq. trunc (the N_occ^2 integrations) and
+//    the Hartree part of f_Hxc in Eq. k1eterm;
+//  * contract: R_v = c_K phi_v (v_H + f_xc drho) - alpha sum_v' tau_vv' a_v'
+//    (the K1e and K1d integrands of Eqs. k1eterm and k1d before projection).
+//
+// Real fields are stored as f[(i0*n1 + i1)*n2 + i2].  A 3D transform is a
+// stick pass (1D FFTs along i0 of the columns (k1, k2) that can be nonzero)
+// and a plane pass (2D FFT over (i1, i2) at fixed i0, staged in LDS).  Two real
+// fields travel as the real and imaginary parts of one complex field (the
+// Gamma-point packing).  Stick data layout: [pack][i0 or k0][stick].
+#include "wtd_internal.h"
+
+namespace wtd {
+
+namespace {
+
+constexpr int kStickThreads = 256;
+constexpr int kPlaneThreads = 512;
+
+int min_radix(const FFTPlan& p) {
+  int r = 8;
+  for (int i = 0; i < p.np; ++i) r = p.rad[i] < r ? p.rad[i] : r;
+  return r;
+}
+
+int pick_maxb(int nlines, const FFTPlan& p, int nthreads) {
+  int64_t total = (int64_t)nlines * (p.n / min_radix(p));
+  int64_t need = (total + nthreads - 1) / nthreads;
+  if (need <= 1) return 1;
+  if (need <= 2) return 2;
+  if (need <= 4) return 4;
+  if (need <= 8) return 8;
+  throw StatusError{WTD_ERR_SHAPE, "FFT line batch too large for one workgroup"};
+}
+
+#define WTD_MAXB_DISPATCH(maxb, ...)                              \
+  switch (maxb) {                                                 \
+    case 1: { constexpr int MB = 1; __VA_ARGS__; } break;         \
+    case 2: { constexpr int MB = 2; __VA_ARGS__; } break;         \
+    case 4: { constexpr int MB = 4; __VA_ARGS__; } break;         \
+    default: { constexpr int MB = 8; __VA_ARGS__; } break;        \
+  }
+
+// 2D FFT of the LDS plane [k1][k2] (k2 fastest): S = -1 rows first then columns
+// (forward), S = +1 columns first then rows (inverse).  Either order gives the
+// same 2D transform; the order only matters for future pruning.
+template <int S, int MB1, int MB2, typename T>
+__device__ __forceinline__ void plane_fft(cplx<T>* pl, const FFTPlan& P1, const FFTPlan& P2,
+                                          int n1, int n2, const cplx<T>* tw1,
+                                          const cplx<T>* tw2) {
+  if (S < 0) {
+    lds_fft<S, MB2, false>(pl, P2, n1, 1, n2, tw2);   // along i2: n1 rows
+    lds_fft<S, MB1, true>(pl, P1, n2, n2, 1, tw1);    // along i1: n2 columns
+  } else {
+    lds_fft<S, MB1, true>(pl, P1, n2, n2, 1, tw1);
+    lds_fft<S, MB2, false>(pl, P2, n1, 1, n2, tw2);
+  }
+}
+
+// ---------------------------------------------------------------- sphere -> sticks
+// coef: [nb][per_trial][npw][2]; pack (b, j) carries fields v = 2j (re) and 2j+1 (im).
+template <int MB, typename T>
+__global__ void __launch_bounds__(kStickThreads)
+k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw, int n0, int nw,
+                    const int* __restrict__ off, const int4* __restrict__ ent, FFTPlan P0,
+                    const cplx<T>* __restrict__ tw0, cplx<T>* __restrict__ wst) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tile = blockIdx.x;
+  const int pack = blockIdx.y;
+  const int b = pack / npt, j = pack - b * npt;
+  const int v1 = 2 * j, v2 = 2 * j + 1;
+  const T* c1 = coef + ((int64_t)b * per_trial + v1) * npw * 2;
+  const T* c2 = (v2 < per_trial) ? c1 + (int64_t)npw * 2 : nullptr;
+  const int tot = n0 * kStickTile;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) buf[i] = {T(0), T(0)};
+  __syncthreads();
+  for (int e = off[tile] + threadIdx.x; e < off[tile + 1]; e += blockDim.x) {
+    const int4 q = ent[e];  // (h, sign, local stick, k0)
+    const int h = q.x;
+    T ar = c1[2 * h], ai = c1[2 * h + 1];
+    T br = c2 ? c2[2 * h] : T(0), bi = c2 ? c2[2 * h + 1] : T(0);
+    cplx<T> z;
+    if (h == 0) {
+      z = {ar, br};
+    } else if (q.y > 0) {
+      z = {ar - bi, ai + br};          // c1(m) + i c2(m)
+    } else {
+      z = {ar + bi, br - ai};          // conj(c1(m)) + i conj(c2(m))
+    }
+    buf[q.w * kStickTile + q.z] = z;
+  }
+  __syncthreads();
+  lds_fft<+1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  cplx<T>* out = wst + (int64_t)pack * n0 * nw;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+    const int s = tile * kStickTile + l;
+    if (s < nw) out[(int64_t)i0 * nw + s] = buf[i];
+  }
+}
+
+// ---------------------------------------------------------------- sticks -> real fields
+// One workgroup per (i0, trial b); loops over the packs of that trial.  With
+// drho != nullptr also forms drho_b = sum_v phi_v out_bv on the plane.
+template <int MB1, int MB2, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int n0, int n1,
+                    int n2, int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                    const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, T scale,
+                    T* __restrict__ out, const T* __restrict__ phi, T* __restrict__ drho) {
+  extern __shared__ unsigned char smem_raw[];
+  const int plane = n1 * n2;
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* acc = reinterpret_cast<T*>(pl + plane);
+  const int i0 = blockIdx.x;
+  const int b = blockIdx.y;
+  const int64_t nr = (int64_t)n0 * plane;
+  const int64_t poff = (int64_t)i0 * plane;
+  if (drho)
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) acc[i] = T(0);
+  for (int j = 0; j < npt; ++j) {
+    const int pack = b * npt + j;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
+    __syncthreads();
+    const cplx<T>* src = wst + ((int64_t)pack * n0 + i0) * nw;
+    for (int s = threadIdx.x; s < nw; s += blockDim.x) pl[k12[s]] = src[s];
+    __syncthreads();
+    plane_fft<+1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+    const int v1 = 2 * j, v2 = 2 * j + 1;
+    T* o1 = out + ((int64_t)b * per_trial + v1) * nr + poff;
+    T* o2 = o1 + nr;
+    const bool has2 = v2 < per_trial;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      const cplx<T> z = pl[i];
+      const T a = z.x * scale, c = z.y * scale;
+      o1[i] = a;
+      if (has2) o2[i] = c;
+      if (drho) {
+        T d = phi[(int64_t)v1 * nr + poff + i] * a;
+        if (has2) d += phi[(int64_t)v2 * nr + poff + i] * c;
+        acc[i] += d;
+      }
+    }
+    __syncthreads();
+  }
+  if (drho) {
+    T* d = drho + (int64_t)b * nr + poff;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) d[i] = acc[i];
+  }
+}
+
+// ---------------------------------------------------------------- pair products -> density sticks
+// quad (a, b, c, d): re = src[a]*src[b] (or src[a] if b < 0), im likewise from (c, d);
+// c < 0 means no imaginary part.
+template <int MB1, int MB2, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, int limit, int n0,
+                   int n1, int n2, int nd, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                   const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+                   cplx<T>* __restrict__ dst) {
+  extern __shared__ unsigned char smem_raw[];
+  const int plane = n1 * n2;
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int i0 = blockIdx.x;
+  const int pack = blockIdx.y;
+  const int64_t nr = (int64_t)n0 * plane;
+  const int64_t poff = (int64_t)i0 * plane;
+  int4 q = quads[pack];
+  if (q.z >= limit) q.z = -1;  // packs past the last valid field carry no imaginary part
+  const T* fa = src + (int64_t)q.x * nr + poff;
+  const T* fb = q.y >= 0 ? src + (int64_t)q.y * nr + poff : nullptr;
+  const T* fc = q.z >= 0 ? src + (int64_t)q.z * nr + poff : nullptr;
+  const T* fd = q.w >= 0 ? src + (int64_t)q.w * nr + poff : nullptr;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+    T re = fb ? fa[i] * fb[i] : fa[i];
+    T im = fc ? (fd ? fc[i] * fd[i] : fc[i]) : T(0);
+    pl[i] = {re, im};
+  }
+  __syncthreads();
+  plane_fft<-1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+  cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nd;
+  for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
+}
+
+// ---------------------------------------------------------------- Poisson on density sticks
+// forward FFT along i0, multiply by the kernel 4 pi/|G|^2 / N_r (v_g0/N_r at G = 0),
+// inverse FFT along i0; in place.
+template <int MB, typename T>
+__global__ void __launch_bounds__(kStickThreads)
+k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict__ kern,
+                 FFTPlan P0, const cplx<T>* __restrict__ tw0) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tile = blockIdx.x;
+  const int pack = blockIdx.y;
+  cplx<T>* base = dst + (int64_t)pack * n0 * nd;
+  const int tot = n0 * kStickTile;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+    const int s = tile * kStickTile + l;
+    buf[i] = (s < nd) ? base[(int64_t)i0 * nd + s] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  lds_fft<-1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int k0 = i / kStickTile, l = i - k0 * kStickTile;
+    const int s = tile * kStickTile + l;
+    const T kv = (s < nd) ? kern[(int64_t)s * n0 + k0] : T(0);
+    buf[i] = cscale(buf[i], kv);
+  }
+  __syncthreads();
+  lds_fft<+1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+    const int s = tile * kStickTile + l;
+    if (s < nd) base[(int64_t)i0 * nd + s] = buf[i];
+  }
+}
+
+// ---------------------------------------------------------------- density sticks -> real fields
+template <int MB1, int MB2, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1, int n2, int nd,
+                    const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                    const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+                    T* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  const int plane = n1 * n2;
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int i0 = blockIdx.x;
+  const int pack = blockIdx.y;
+  const int64_t nr = (int64_t)n0 * plane;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
+  __syncthreads();
+  const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nd;
+  for (int s = threadIdx.x; s < nd; s += blockDim.x) pl[k12[s]] = src[s];
+  __syncthreads();
+  plane_fft<+1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+  T* o1 = out + (int64_t)(2 * pack) * nr + (int64_t)i0 * plane;
+  T* o2 = o1 + nr;
+  const bool has2 = 2 * pack + 1 < nfield;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+    const cplx<T> z = pl[i];
+    o1[i] = z.x;
+    if (has2) o2[i] = z.y;
+  }
+}
+
+// ---------------------------------------------------------------- real fields -> wave sticks
+template <int MB1, int MB2, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int n0, int n1, int n2,
+                    int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                    const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+                    cplx<T>* __restrict__ wst) {
+  extern __shared__ unsigned char smem_raw[];
+  const int plane = n1 * n2;
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int i0 = blockIdx.x;
+  const int pack = blockIdx.y;
+  const int b = pack / npt, j = pack - b * npt;
+  const int v1 = 2 * j, v2 = 2 * j + 1;
+  const int64_t nr = (int64_t)n0 * plane;
+  const T* f1 = fields + ((int64_t)b * per_trial + v1) * nr + (int64_t)i0 * plane;
+  const T* f2 = (v2 < per_trial) ? f1 + nr : nullptr;
+  for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {f1[i], f2 ? f2[i] : T(0)};
+  __syncthreads();
+  plane_fft<-1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+  cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nw;
+  for (int s = threadIdx.x; s < nw; s += blockDim.x) o[s] = pl[k12[s]];
+}
+
+// ---------------------------------------------------------------- wave sticks: forward along i0
+template <int MB, typename T>
+__global__ void __launch_bounds__(kStickThreads)
+k_wsticks_forward(cplx<T>* __restrict__ wst, int n0, int nw, FFTPlan P0,
+                  const cplx<T>* __restrict__ tw0) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tile = blockIdx.x;
+  const int pack = blockIdx.y;
+  cplx<T>* base = wst + (int64_t)pack * n0 * nw;
+  const int tot = n0 * kStickTile;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+    const int s = tile * kStickTile + l;
+    buf[i] = (s < nw) ? base[(int64_t)i0 * nw + s] : cplx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  lds_fft<-1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int k0 = i / kStickTile, l = i - k0 * kStickTile;
+    const int s = tile * kStickTile + l;
+    if (s < nw) base[(int64_t)k0 * nw + s] = buf[i];
+  }
+}
+
+// ---------------------------------------------------------------- unpack to half-sphere coefficients
+// F1(m) = (Z(m) + conj Z(-m)) / 2, F2(m) = (Z(m) - conj Z(-m)) / (2i), times scale.
+template <typename T>
+__global__ void k_extract_sphere(const cplx<T>* __restrict__ wst, int npt, int per_trial,
+                                 int n0, int nw, int npw, const int2* __restrict__ pos, T scale,
+                                 T* __restrict__ coef) {
+  const int pack = blockIdx.y;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= npw) return;
+  const int b = pack / npt, j = pack - b * npt;
+  const int v1 = 2 * j, v2 = 2 * j + 1;
+  const cplx<T>* base = wst + (int64_t)pack * n0 * nw;
+  const int2 ps = pos[h];
+  const cplx<T> zp = base[ps.x], zm = base[ps.y];
+  const T hs = T(0.5) * scale;
+  T* c1 = coef + (((int64_t)b * per_trial + v1) * npw + h) * 2;
+  c1[0] = (zp.x + zm.x) * hs;
+  c1[1] = (zp.y - zm.y) * hs;
+  if (v2 < per_trial) {
+    T* c2 = c1 + (int64_t)npw * 2;
+    c2[0] = (zp.y + zm.y) * hs;
+    c2[1] = (zm.x - zp.x) * hs;
+  }
+}
+
+// ---------------------------------------------------------------- exchange + response contraction
+// R[b][v](r) = c_K phi_v(r) (v_H,b(r) + f_xc(r) drho_b(r)) - alpha sum_v' tau_vv'(r) a~[b][v'](r)
+// Tile: 64 points x 16 occupied rows x 16 trials; loop over v' in chunks of 4
+// staged in LDS.  Each thread owns one point and 4 rows (64 accumulators).
+constexpr int kCtPts = 64, kCtV = 16, kCtB = 16, kCtVp = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_contract(int nb, int nocc, int64_t nr, int ntile, int nvb, const T* __restrict__ phi,
+           const T* __restrict__ at, const T* __restrict__ tau, const int* __restrict__ pidx,
+           const T* __restrict__ vh, const T* __restrict__ drho, const T* __restrict__ fxc,
+           T ck, T alpha, int k1e, int k1d, T* __restrict__ R) {
+  __shared__ T s_tau[kCtV][kCtVp][kCtPts];
+  __shared__ T s_at[kCtB][kCtVp][kCtPts];
+  // XCD-aware order: consecutive dispatch slots on one XCD are the v-blocks of
+  // one point tile, so the trial fields of that tile are shared through L2.
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, slot = bid >> 3;
+  const int vb = slot % nvb;
+  const int tile = (slot / nvb) * 8 + xcd;
+  if (tile >= ntile) return;
+  const int64_t r0 = (int64_t)tile * kCtPts;
+  const int tid = threadIdx.x;
+  const int pt = tid & (kCtPts - 1);
+  const int vs = tid >> 6;  // 0..3
+  const int64_t r = r0 + pt;
+  const bool rin = r < nr;
+  for (int b0 = 0; b0 < nb; b0 += kCtB) {
+    T acc[4][kCtB];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int bb = 0; bb < kCtB; ++bb) acc[a][bb] = T(0);
+    if (k1d) {
+      for (int vp0 = 0; vp0 < nocc; vp0 += kCtVp) {
+        // stage tau[v-block][vp chunk][pts] and at[b chunk][vp chunk][pts]
+        for (int e = tid; e < kCtV * kCtVp * kCtPts; e += 256) {
+          const int p = e & (kCtPts - 1), q = e >> 6;
+          const int vv = q / kCtVp, vp = q - vv * kCtVp;
+          const int v = vb * kCtV + vv, vpa = vp0 + vp;
+          const int64_t rr = r0 + p;
+          T val = T(0);
+          if (v < nocc && vpa < nocc && rr < nr) val = tau[(int64_t)pidx[v * nocc + vpa] * nr + rr];
+          s_tau[vv][vp][p] = val;
+        }
+        for (int e = tid; e < kCtB * kCtVp * kCtPts; e += 256) {
+          const int p = e & (kCtPts - 1), q = e >> 6;
+          const int bb = q / kCtVp, vp = q - bb * kCtVp;
+          const int b = b0 + bb, vpa = vp0 + vp;
+          const int64_t rr = r0 + p;
+          T val = T(0);
+          if (b < nb && vpa < nocc && rr < nr) val = at[((int64_t)b * nocc + vpa) * nr + rr];
+          s_at[bb][vp][p] = val;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int vp = 0; vp < kCtVp; ++vp) {
+          T t[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) t[a] = s_tau[vs * 4 + a][vp][pt];
+#pragma unroll
+          for (int bb = 0; bb < kCtB; ++bb) {
+            const T x = s_at[bb][vp][pt];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][bb] += t[a] * x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (rin) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int v = vb * kCtV + vs * 4 + a;
+        if (v >= nocc) continue;
+        const T ph = phi[(int64_t)v * nr + r];
+        for (int bb = 0; bb < kCtB; ++bb) {
+          const int b = b0 + bb;
+          if (b >= nb) break;
+          T val = -alpha * acc[a][bb];
+          if (k1e) {
+            const T d = drho[(int64_t)b * nr + r];
+            val += ck * ph * (vh[(int64_t)b * nr + r] + fxc[r] * d);
+          }
+          R[((int64_t)b * nocc + v) * nr + r] = val;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- small elementwise kernels
+template <typename T>
+__global__ void k_dterm_combine(int nb, int nocc, int nc, const T* __restrict__ S,
+                                const T* __restrict__ Q, const double* __restrict__ eo,
+                                const double* __restrict__ ec, int with_d, T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)nb * nocc * nc;
+  if (i >= tot) return;
+  const int c = (int)(i % nc);
+  const int v = (int)((i / nc) % nocc);
+  T val = Q[i];
+  if (with_d) val += (T)(ec[c] - eo[v]) * S[i];
+  out[i] = val;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (Tout)in[i];
+}
+
+__global__ void k_transition_out(int nb, int nocc, int nc, const void* __restrict__ Q, int qf,
+                                 const double* __restrict__ X, const double* __restrict__ eo,
+                                 const double* __restrict__ ec, int with_d,
+                                 double* __restrict__ T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)nb * nocc * nc;
+  if (i >= tot) return;
+  const int c = (int)(i % nc);
+  const int v = (int)((i / nc) % nocc);
+  double q = qf ? (double)reinterpret_cast<const float*>(Q)[i]
+                : reinterpret_cast<const double*>(Q)[i];
+  if (with_d) q += (ec[c] - eo[v]) * X[i];
+  T[i] = q;
+}
+
+template <typename F>
+void set_lds(F* func, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(func),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void check_lds(size_t bytes) {
+  WTD_REQUIRE(bytes <= 160 * 1024, WTD_ERR_SHAPE,
+              "grid plane does not fit in 160 KB of LDS for this precision");
+}
+
+}  // namespace
+
+// ============================================================================ launchers
+template <typename T>
+void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
+                              int per_trial, cplx<T>* wst, hipStream_t s) {
+  (void)nfield;
+  const int npt = (per_trial + 1) / 2;
+  dim3 grid(g.nwtile, nb * npt);
+  const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
+  const int mb = pick_maxb(kStickTile, g.plan0, kStickThreads);
+  WTD_MAXB_DISPATCH(mb, {
+    set_lds((k_sphere_to_wsticks<MB, T>), lds);
+    hipLaunchKernelGGL((k_sphere_to_wsticks<MB, T>), grid, dim3(kStickThreads), lds, s, coef, per_trial, npt, npw, g.n0,
+                       g.nw, g.wtile_off, g.wtile_ent, g.plan0,
+                       static_cast<const cplx<T>*>(g.tw0), wst);
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+#define WTD_PLANE_DISPATCH(mb1, mb2, ...)                                    \
+  WTD_MAXB_DISPATCH(mb1, {                                                   \
+    constexpr int M1 = MB;                                                   \
+    WTD_MAXB_DISPATCH(mb2, { constexpr int M2 = MB; __VA_ARGS__; });         \
+  })
+
+template <typename T>
+void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
+                              int nfield_per_trial, T scale, T* out, const T* phi, T* drho,
+                              hipStream_t s) {
+  (void)nfield_per_trial;
+  const int npt = (per_trial + 1) / 2;
+  dim3 grid(g.n0, nb);
+  const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
+  check_lds(lds);
+  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
+  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
+  WTD_PLANE_DISPATCH(mb1, mb2, {
+    set_lds((k_wsticks_to_fields<M1, M2, T>), lds);
+    hipLaunchKernelGGL((k_wsticks_to_fields<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, wst, npt, per_trial, g.n0, g.n1,
+                       g.n2, g.nw, g.wst_k12, g.plan1, g.plan2,
+                       static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2),
+                       scale, out, phi, drho);
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads, int npack,
+                             int limit, cplx<T>* dst, hipStream_t s) {
+  dim3 grid(g.n0, npack);
+  const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
+  check_lds(lds);
+  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
+  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
+  WTD_PLANE_DISPATCH(mb1, mb2, {
+    set_lds((k_pairs_to_dsticks<M1, M2, T>), lds);
+    hipLaunchKernelGGL((k_pairs_to_dsticks<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, src, quads, limit, g.n0, g.n1, g.n2, g.nd,
+                       g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                       static_cast<const cplx<T>*>(g.tw2), dst);
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s) {
+  dim3 grid((g.nd + kStickTile - 1) / kStickTile, npack);
+  const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
+  const int mb = pick_maxb(kStickTile, g.plan0, kStickThreads);
+  WTD_MAXB_DISPATCH(mb, {
+    set_lds((k_dstick_poisson<MB, T>), lds);
+    hipLaunchKernelGGL((k_dstick_poisson<MB, T>), grid, dim3(kStickThreads), lds, s, dst, g.n0, g.nd,
+                       static_cast<const T*>(g.dkern), g.plan0,
+                       static_cast<const cplx<T>*>(g.tw0));
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, int nfield,
+                              T* out, hipStream_t s) {
+  dim3 grid(g.n0, npack);
+  const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
+  check_lds(lds);
+  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
+  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
+  WTD_PLANE_DISPATCH(mb1, mb2, {
+    set_lds((k_dsticks_to_fields<M1, M2, T>), lds);
+    hipLaunchKernelGGL((k_dsticks_to_fields<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, dst, nfield, g.n0, g.n1, g.n2, g.nd,
+                       g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                       static_cast<const cplx<T>*>(g.tw2), out);
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int per_trial,
+                              int nfield_per_trial, cplx<T>* wst, hipStream_t s) {
+  (void)nfield_per_trial;
+  const int npt = (per_trial + 1) / 2;
+  dim3 grid(g.n0, nb * npt);
+  const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
+  check_lds(lds);
+  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
+  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
+  WTD_PLANE_DISPATCH(mb1, mb2, {
+    set_lds((k_fields_to_wsticks<M1, M2, T>), lds);
+    hipLaunchKernelGGL((k_fields_to_wsticks<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, fields, npt, per_trial, g.n0, g.n1,
+                       g.n2, g.nw, g.wst_k12, g.plan1, g.plan2,
+                       static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2),
+                       wst);
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_wsticks_to_sphere(const Geometry& g, cplx<T>* wst, int npack, hipStream_t s) {
+  dim3 grid((g.nw + kStickTile - 1) / kStickTile, npack);
+  const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
+  const int mb = pick_maxb(kStickTile, g.plan0, kStickThreads);
+  WTD_MAXB_DISPATCH(mb, {
+    set_lds((k_wsticks_forward<MB, T>), lds);
+    hipLaunchKernelGGL((k_wsticks_forward<MB, T>), grid, dim3(kStickThreads), lds, s, wst, g.n0, g.nw, g.plan0,
+                       static_cast<const cplx<T>*>(g.tw0));
+  });
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_extract_sphere(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
+                           int nfield_per_trial, int npw, T scale, T* coef, hipStream_t s) {
+  (void)nfield_per_trial;
+  const int npt = (per_trial + 1) / 2;
+  dim3 grid((npw + 255) / 256, nb * npt);
+  hipLaunchKernelGGL(k_extract_sphere<T>, grid, dim3(256), 0, s, wst, npt, per_trial, g.n0, g.nw,
+                     npw, g.sph_pos, scale, coef);
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_contract(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
+                     const T* tau, const int* pair_index, const T* vh, const T* drho,
+                     const T* fxc, T ck, T alpha, bool k1e, bool k1d, T* R, hipStream_t s) {
+  const int ntile = (int)((g.nr + kCtPts - 1) / kCtPts);
+  const int nvb = (nocc + kCtV - 1) / kCtV;
+  const int ntile8 = (ntile + 7) / 8 * 8;
+  const int64_t nblk = (int64_t)ntile8 * nvb;
+  WTD_REQUIRE(nblk < (1ll << 31), WTD_ERR_SHAPE, "contraction grid too large");
+  hipLaunchKernelGGL(k_contract<T>, dim3((unsigned)nblk), dim3(256), 0, s, nb, nocc, g.nr, ntile,
+                     nvb, phi, at, tau, pair_index, vh, drho, fxc, ck, alpha, (int)k1e, (int)k1d,
+                     R);
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_dterm_combine(int nb, int nocc, int nc, const T* S, const T* Q, const double* eo,
+                          const double* ec, bool with_d, T* out, hipStream_t s) {
+  const int64_t tot = (int64_t)nb * nocc * nc;
+  hipLaunchKernelGGL(k_dterm_combine<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     nb, nocc, nc, S, Q, eo, ec, (int)with_d, out);
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename Tin, typename Tout>
+void launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     in, out, n);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_float,
+                           const double* X, const double* eo, const double* ec, bool with_d,
+                           double* T, hipStream_t s) {
+  const int64_t tot = (int64_t)nb * nocc * nc;
+  hipLaunchKernelGGL(k_transition_out, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, nb,
+                     nocc, nc, Q, (int)q_is_float, X, eo, ec, (int)with_d, T);
+  WTD_HIP(hipGetLastError());
+}
+
+#define WTD_INST(T)                                                                            \
+  template void launch_sphere_to_wsticks<T>(const Geometry&, const T*, int, int, int, int,     \
+                                            cplx<T>*, hipStream_t);                            \
+  template void launch_wsticks_to_fields<T>(const Geometry&, const cplx<T>*, int, int, int, T, \
+                                            T*, const T*, T*, hipStream_t);                    \
+  template void launch_pairs_to_dsticks<T>(const Geometry&, const T*, const int4*, int, int,   \
+                                           cplx<T>*, hipStream_t);                             \
+  template void launch_dstick_poisson<T>(const Geometry&, cplx<T>*, int, hipStream_t);         \
+  template void launch_dsticks_to_fields<T>(const Geometry&, const cplx<T>*, int, int, T*,     \
+                                            hipStream_t);                                      \
+  template void launch_fields_to_wsticks<T>(const Geometry&, const T*, int, int, int,          \
+                                            cplx<T>*, hipStream_t);                            \
+  template void launch_wsticks_to_sphere<T>(const Geometry&, cplx<T>*, int, hipStream_t);      \
+  template void launch_extract_sphere<T>(const Geometry&, const cplx<T>*, int, int, int, int,  \
+                                         T, T*, hipStream_t);                                  \
+  template void launch_contract<T>(const Geometry&, int, int, const T*, const T*, const T*,    \
+                                   const int*, const T*, const T*, const T*, T, T, bool, bool, \
+                                   T*, hipStream_t);                                           \
+  template void launch_dterm_combine<T>(int, int, int, const T*, const T*, const double*,      \
+                                        const double*, bool, T*, hipStream_t);
+
+WTD_INST(float)
+WTD_INST(double)
+
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template void launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
+
+}  // namespace wtd

@@ -1,0 +1,166 @@
+"""Parity of the HIP Liouville apply with the FP64 oracle (needs an MI355X).
+
+Per-term checks (D, K1e, K1d separately, then all) because the K terms are
+small next to D: a K-term bug could hide under a whole-operator tolerance.
+Bar: FP64 per-trial relative error <= 1e-10; FP32 <= 2e-5 (FP32 arithmetic
+through ~10 rounding steps on O(1) values, with headroom)."""
+import numpy as np
+import pytest
+
+import oracle
+from gen import trials_in_span, trials_random
+from tests.gpu_util import rel_err, say, to_complex
+
+pytestmark = pytest.mark.gpu
+
+TERMS = {"D": 1, "K1E": 2, "K1D": 4, "ALL": 7}
+
+
+def _ctx(s, nb, prec="fp64", terms=7):
+    from paper_2309_03513_amd import Liouville
+    return Liouville(s, max_nb=nb, precision=prec, terms=terms)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "p1", "p2"])
+@pytest.mark.parametrize("term", ["D", "K1E", "K1D", "ALL"])
+def test_apply_fp64_per_term(systems, cfg, term):
+    s = systems(cfg)
+    nb = s.cfg.nb
+    a = trials_random(s, nb)          # not in the conduction span: exercises the projection
+    say(f"apply fp64 cfg={cfg} term={term} nb={nb}")
+    L = _ctx(s, nb, "fp64", TERMS[term])
+    got = to_complex(L.apply(a))
+    L.close()
+    ref = oracle.apply_liouville(s, a, terms=TERMS[term])
+    err = rel_err(got, ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", ["c1", "p1"])
+def test_apply_fp32(systems, cfg):
+    s = systems(cfg)
+    nb = s.cfg.nb
+    a, _ = trials_in_span(s, nb)
+    say(f"apply fp32 cfg={cfg}")
+    for term in ("K1E", "K1D", "ALL"):
+        L = _ctx(s, nb, "fp32", TERMS[term])
+        got = to_complex(L.apply(a))
+        L.close()
+        ref = oracle.apply_liouville(s, a, terms=TERMS[term])
+        err = rel_err(got, ref)
+        say(f"  term={term} rel err {err:.3e}")
+        assert err <= 2e-5
+
+
+def test_apply_nb_smaller_than_max_and_odd(systems):
+    s = systems("p1")
+    a = trials_random(s, 3)
+    say("apply nb=3 on a max_nb=6 context, then nb=1")
+    L = _ctx(s, 6)
+    for nb in (3, 1):
+        got = to_complex(L.apply(a[:nb]))
+        ref = oracle.apply_liouville(s, a[:nb])
+        assert rel_err(got, ref) <= 1e-10
+    L.close()
+
+
+def test_transition_apply_matches_oracle(systems):
+    s = systems("p2")
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((3, s.nocc, s.ncond))
+    say("apply_transition fp64 p2")
+    L = _ctx(s, 3)
+    got = L.apply_transition(X).cpu().numpy()
+    L.close()
+    ref = oracle.apply_transition(s, X)
+    assert rel_err(got, ref) <= 1e-10
+
+
+def test_deterministic_bitwise(systems):
+    s = systems("p1")
+    a = trials_random(s, 5)
+    say("determinism fp64 p1")
+    L = _ctx(s, 5)
+    r1 = L.apply(a).cpu().numpy()
+    r2 = L.apply(a).cpu().numpy()
+    L.close()
+    assert np.array_equal(r1, r2)
+
+
+def test_v_g0_and_scales(systems):
+    s = systems("p2").replace(v_g0=0.9, alpha=0.45, c_k=1.0)
+    a = trials_random(s, 2)
+    say("v_g0 = 0.9, alpha = 0.45, c_K = 1")
+    L = _ctx(s, 2)
+    got = to_complex(L.apply(a))
+    L.close()
+    assert rel_err(got, oracle.apply_liouville(s, a)) <= 1e-10
+
+
+def test_set_occ_rotation_invariance(systems):
+    """K terms with rotated occupied orbitals: L_K(Phi U, A U) = L_K(Phi, A) U."""
+    s = systems("p2")
+    U, _ = np.linalg.qr(np.random.default_rng(9).standard_normal((s.nocc, s.nocc)))
+    a = trials_random(s, 2)
+    say("set_occ rotation invariance p2")
+    L = _ctx(s, 2, terms=6)
+    base = to_complex(L.apply(a))
+    L.set_occ(U.T @ s.c_occ)
+    rot = to_complex(L.apply(np.einsum("vn,bvm->bnm", U, a)))
+    L.close()
+    assert rel_err(rot, np.einsum("vn,bvm->bnm", U, base)) <= 1e-10
+
+
+def test_davidson_c1_matches_dense(systems):
+    s = systems("c1")
+    n = s.nocc * s.ncond
+    M = oracle.apply_transition(s, np.eye(n).reshape(n, s.nocc, s.ncond)).reshape(n, n)
+    ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+    say("davidson fp64 c1")
+    L = _ctx(s, 4)
+    omega, x, resid, nit, st = L.davidson(4, 4, tol=1e-8, max_iter=100)
+    say(f"  omega={omega} resid={resid} iters={nit} status={st}")
+    assert st == 0
+    assert np.all(resid <= 1e-8)
+    assert np.max(np.abs(omega - ev[:4]) / np.abs(ev[:4])) <= 1e-10
+    xc = to_complex(x)
+    nrm = oracle.gamma_inner(xc, xc).sum(axis=1)
+    assert np.abs(nrm - 1).max() < 1e-10
+    # eigenvector check through the oracle: L x = omega x
+    lx = oracle.apply_liouville(s, xc)
+    assert rel_err(lx, omega[:, None, None] * xc) < 1e-7
+    L.close()
+
+
+def test_davidson_fp32_within_1mev(systems):
+    s = systems("c1")
+    n = s.nocc * s.ncond
+    M = oracle.apply_transition(s, np.eye(n).reshape(n, s.nocc, s.ncond)).reshape(n, n)
+    ev = np.linalg.eigvalsh(0.5 * (M + M.T))
+    say("davidson fp32 c1")
+    L = _ctx(s, 4, "fp32")
+    omega, x, resid, nit, st = L.davidson(4, 4, tol=1e-5, max_iter=100)
+    L.close()
+    say(f"  |d omega| = {np.abs(omega - ev[:4]).max():.3e} Ha")
+    assert np.abs(omega - ev[:4]).max() <= 3.674932e-5
+
+
+def test_error_codes(systems):
+    from paper_2309_03513_amd import WtdError
+    s = systems("c1")
+    L = _ctx(s, 2)
+    a = trials_random(s, 3)
+    say("error codes")
+    with pytest.raises(WtdError) as e:
+        L.apply(a)                      # nb = 3 > max_nb = 2
+    assert e.value.status == -2
+    with pytest.raises(WtdError) as e:
+        L.apply_bwd(a[:1], a[:1])
+    assert e.value.status == -5
+    with pytest.raises(WtdError) as e:
+        L.davidson(3, 2)                # nroots > nb
+    assert e.value.status == -2
+    om, x, r, nit, st = L.davidson(2, 2, tol=1e-14, max_iter=1)
+    assert st == 1                      # WTD_NOT_CONVERGED is a warning
+    L.close()
