@@ -1,0 +1,223 @@
+"""Benchmark: Liouville trial-vector applies/s on one MI355X.
+
+One step = one wtd_apply_liouville on a block of Nb = 16 trial vectors of the
+72^3 / Nocc = 128 synthetic system (every stage of the hot path: projection,
+trial transforms, density response + Hartree, all Nocc(Nocc+1)/2 pair Poisson
+solves, exchange contraction, output transforms, projection).  The FP32-bulk
+path is the headline value; the FP64 path is timed beside it, and the FP32
+path's 8 lowest excitation energies are checked against the FP64 oracle's
+(tests/golden/roots_c2.json) to the 1 meV bar.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-accuracy]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MEV = 3.674932e-5  # Hartree per meV
+METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at ΔE≤1 meV"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(s, nb, sz, nd, nw, chunk_packs):
+    """Algorithmic HBM bytes per launch of the single-kernel stages."""
+    nr = int(np.prod(s.n))
+    n0 = s.n[0]
+    nocc = s.nocc
+    npairs = nocc * (nocc + 1) // 2
+    npack = (npairs + 1) // 2
+    # pair Poisson is launched in chunks of `chunk_packs` packed pairs; use the average chunk
+    nchunks = (npack + chunk_packs - 1) // chunk_packs
+    avg_packs = npack / nchunks
+    dstick = avg_packs * n0 * nd * 2 * sz
+    out = {
+        # reads the occupied orbitals the chunk touches (all of them, once), writes sticks
+        "pair_plane_fwd": dstick + nocc * nr * sz,
+        "pair_stick_poisson": 2 * dstick,
+        # reads sticks, writes the chunk's pair potentials
+        "pair_plane_inv": dstick + 2 * avg_packs * nr * sz,
+        # reads every pair potential once, the projected trials, phi, v_H, drho, f_xc;
+        # writes R
+        "contract": (npairs + 2 * nb * nocc + nocc + 2 * nb + 1) * nr * sz,
+    }
+    return out
+
+
+def run_precision(s, prec, nb, steps, warmup, a_np):
+    import torch
+    from paper_2309_03513_amd import Liouville
+    L = Liouville(s, max_nb=nb, precision=prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    a = torch.tensor(np.stack([a_np.real, a_np.imag], -1), dtype=dt, device="cuda").contiguous()
+    out = torch.empty_like(a)
+    for i in range(warmup):
+        L.apply(a, out=out)
+    torch.cuda.synchronize()
+    L.profile(True)
+    L.profile_read()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        L.apply(a, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = L.profile_read()
+    L.profile(False)
+    ws = L.workspace_bytes()
+    ms = (t1 - t0) * 1e3 / steps
+    log(f"{prec}: {ms:.3f} ms/step, {nb * 1e3 / ms:.1f} applies/s, workspace {ws / 2**30:.1f} GiB")
+    return L, ms, stages, ws
+
+
+def accuracy_fp32(s, nb, nroots):
+    """FP32-bulk Davidson roots vs the oracle's FP64 roots (meV)."""
+    from paper_2309_03513_amd import Liouville
+    path = os.path.join(ROOT, "tests", "golden", "roots_c2.json")
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    L = Liouville(s, max_nb=nb, precision="fp32")
+    t0 = time.perf_counter()
+    om, _, res, nit, st = L.davidson(nroots, nb, tol=1e-5, max_iter=200, want_x=False)
+    t = time.perf_counter() - t0
+    L.close()
+    d = np.abs(np.asarray(om) - np.asarray(ref["roots_hartree"][:nroots])) / MEV
+    log(f"fp32 davidson: {nit} iterations, {t:.2f} s, max |d omega| = {d.max():.4f} meV")
+    return {"max_abs_domega_meV": float(d.max()), "roots": nroots, "davidson_iterations": int(nit),
+            "davidson_seconds": t, "status": int(st),
+            "reference": "oracle FP64 block Davidson, tests/golden/roots_c2.json"}
+
+
+def cpu_baseline(s, nb, a_np, rows=(0, 1, 2)):
+    """Time the oracle on a bounded sample of the same block and extrapolate per row."""
+    import oracle
+    import oracle.planewave as pw
+    cores = len(os.sched_getaffinity(0))
+    pw._WORKERS = cores
+    t0 = time.perf_counter()
+    oracle.apply_liouville(s, a_np, rows=[rows[0]])
+    t1 = time.perf_counter()
+    oracle.apply_liouville(s, a_np, rows=list(rows))
+    t2 = time.perf_counter()
+    t_one, t_many = t1 - t0, t2 - t1
+    t_row = max((t_many - t_one) / (len(rows) - 1), 0.0)
+    t_fixed = max(t_one - t_row, 0.0)
+    t_block = t_fixed + s.nocc * t_row
+    log(f"oracle: fixed {t_fixed:.1f} s, {t_row:.2f} s/row -> {t_block:.0f} s per block")
+    return {"value": nb / t_block, "unit": "trial-vector applies/s", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"oracle apply on the same Nb={nb} block, output rows {list(rows)} and "
+                       f"{[rows[0]]} of {s.nocc} timed ({t_many + t_one:.1f} s of CPU), "
+                       f"block time = fixed {t_fixed:.1f} s + {s.nocc} x {t_row:.2f} s/row"),
+            "seconds_per_block": t_block}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "layout is a design (DESIGN.md), not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from gen import CONFIGS, make_system, trials_in_span
+    import paper_2309_03513_amd  # noqa: F401  (fails loudly without libwtd.so)
+
+    cfg = CONFIGS[args.config]
+    nb = cfg.nb
+    log(f"building system {cfg.name}")
+    s = make_system(cfg)
+    a_np, _ = trials_in_span(s, nb)
+    torch.cuda.init()
+
+    res = {}
+    for prec in (["fp64"] if not args.no_fp64 else []) + ["fp32"]:
+        L, ms, stages, ws = run_precision(s, prec, nb, args.steps, args.warmup, a_np)
+        res[prec] = dict(ms=ms, stages=stages, ws=ws)
+        L.close()
+        del L
+        torch.cuda.empty_cache()
+
+    fp32 = res["fp32"]
+    value = nb * 1e3 / fp32["ms"]
+    # dominant kernel of the FP32 path and its roofline (algorithmic bytes / mean launch time)
+    nd, nw = _stick_counts(s)
+    chunk = min(512, (s.nocc * (s.nocc + 1) // 2 + 1) // 2)
+    ab = stage_bytes(s, nb, 4, nd, nw, chunk)
+    st = {k: v for k, v in fp32["stages"].items() if v[1] > 0}
+    dom = max((k for k in st if k in ab), key=lambda k: st[k][0])
+    dom_ms = st[dom][0] / st[dom][1]
+    achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes_per_launch": ab[dom], "mean_launch_ms": dom_ms}
+
+    acc = None if args.no_accuracy else accuracy_fp32(s, nb, cfg.nroots)
+    cpu = None if args.no_cpu else cpu_baseline(s, nb, a_np)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "trial-vector applies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": fp32["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"{cfg.name}: 72^3 grid, L=13.5 bohr, 40 Ry ({s.npw} half-sphere "
+                                f"plane waves), Nocc=Nc={s.nocc}, Nb={nb} trial block, "
+                                f"alpha={cfg.alpha}, c_K={cfg.c_k}, FP32 bulk"),
+                   "global_batch": nb, "parallelism": "single GPU"},
+        "fp64": ({"value": nb * 1e3 / res["fp64"]["ms"], "ms_per_step": res["fp64"]["ms"]}
+                 if "fp64" in res else None),
+        "fp32_over_fp64": (res["fp64"]["ms"] / fp32["ms"]) if "fp64" in res else None,
+        "accuracy": acc,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _stick_counts(s):
+    """Wave-stick and density-stick counts for the byte model (same rule as the library)."""
+    import math
+    b = 2 * math.pi / np.asarray(s.cell)
+    m = np.asarray(s.mill)
+    n = s.n
+    keys = set()
+    for sg in (1, -1):
+        k1 = np.mod(sg * m[:, 1], n[1])
+        k2 = np.mod(sg * m[:, 2], n[2])
+        keys.update((k1 * n[2] + k2).tolist())
+    nw = len(keys)
+    g2max = float(np.max(np.sum((m * b) ** 2, axis=1)))
+    r1 = int(math.floor(2 * math.sqrt(g2max) / b[1])) + 1
+    r2 = int(math.floor(2 * math.sqrt(g2max) / b[2])) + 1
+    dk = set()
+    for m1 in range(-r1, r1 + 1):
+        for m2 in range(-r2, r2 + 1):
+            if (m1 * b[1]) ** 2 + (m2 * b[2]) ** 2 <= 4 * g2max * (1 + 1e-12):
+                dk.add((m1 % n[1]) * n[2] + (m2 % n[2]))
+    return len(dk), nw
+
+
+if __name__ == "__main__":
+    main()

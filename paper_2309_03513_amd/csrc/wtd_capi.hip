@@ -160,8 +160,8 @@ void prof_next(wtd_ctx* c, int stage) {
   prof_mark(c, stage);
 }
 
+// Sum the recorded stage intervals (synchronises on the last event).
 void prof_collect(wtd_ctx* c) {
-  if (!c->prof.on) return;
   Profiler& P = c->prof;
   if (P.marks.empty()) return;
   WTD_HIP(hipEventSynchronize(P.pool[P.marks.back().second + 1]));
@@ -173,6 +173,13 @@ void prof_collect(wtd_ctx* c) {
   }
   P.marks.clear();
   P.used = 0;
+}
+
+// Called at the end of an operation: events are kept until wtd_profile_read,
+// unless the pool grows large.
+void prof_finish(wtd_ctx* c) {
+  if (!c->prof.on) return;
+  if (c->prof.marks.size() > 4096) prof_collect(c);
 }
 
 // ---------------------------------------------------------------- geometry
@@ -528,7 +535,7 @@ void apply_impl(wtd_ctx* c, int nb, const T* a, T* la) {
                           (c->mask & WTD_TERM_D) != 0, (T*)c->Tm, s);
   launch_gemm<T, false>(F, K, nc, (const T*)c->Tm, nc, (const T*)c->c_cond, K, la, K, s);
   prof_end(c);
-  prof_collect(c);
+  prof_finish(c);
 }
 
 template <typename T>
@@ -547,7 +554,7 @@ void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout) {
   launch_transition_out(nb, nocc, nc, c->Q, sizeof(T) == sizeof(float), X, c->eps_occ,
                         c->eps_cond, (c->mask & WTD_TERM_D) != 0, Tout, s);
   prof_end(c);
-  prof_collect(c);
+  prof_finish(c);
 }
 
 void apply_transition_any(wtd_ctx* c, int nb, const double* X, double* T) {
@@ -867,6 +874,7 @@ wtd_status wtd_davidson(wtd_ctx* ctx, int32_t nroots, int32_t nb, double tol, in
 wtd_status wtd_profile_enable(wtd_ctx* ctx, int32_t on) {
   return guarded([&]() -> wtd_status {
     WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    if (!on) prof_collect(ctx);
     ctx->prof.on = on != 0;
     return WTD_OK;
   });
@@ -877,6 +885,7 @@ wtd_status wtd_profile_read(wtd_ctx* ctx, int32_t n, double* ms, int64_t* calls,
   return guarded([&]() -> wtd_status {
     WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
     Profiler& P = ctx->prof;
+    prof_collect(ctx);
     for (int i = 0; i < std::min<int>(n, Profiler::kStages); ++i) {
       if (ms) ms[i] = P.ms[i];
       if (calls) calls[i] = P.calls[i];
