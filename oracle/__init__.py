@@ -25,3 +25,4 @@ from .liouville import (  # noqa: F401
     transition_diagonal,
 )
 from .davidson import davidson, davidson_transition  # noqa: F401
+from .adjoint import energy, grad_a, grad_occ  # noqa: F401

@@ -1,0 +1,67 @@
+"""Parity at the benchmark workload's full size (72^3 grid, Nocc = 128, Nb = 16).
+
+The oracle computes sampled output rows v one by one (every row needs all 128
+pair potentials of that v); eigenvalues are compared with the oracle's FP64
+Davidson roots stored in tests/golden/roots_c2.json (written by
+tests/golden/make_golden.py from the oracle alone).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gen import trials_in_span
+from tests.gpu_util import rel_err, say, to_complex
+
+pytestmark = pytest.mark.gpu
+
+ROWS = [0, 77, 127]
+MEV = 3.674932e-5
+
+
+@pytest.fixture(scope="module")
+def c2(systems):
+    s = systems("c2")
+    a, _ = trials_in_span(s, 16)
+    say("oracle rows for the 72^3 / Nocc=128 block")
+    ref = oracle.apply_liouville(s, a, rows=ROWS)
+    return s, a, ref
+
+
+def _golden():
+    path = os.path.join(os.path.dirname(__file__), "golden", "roots_c2.json")
+    return np.asarray(json.load(open(path))["roots_hartree"])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_c2_sampled_rows(c2, prec, tol):
+    from paper_2309_03513_amd import Liouville
+    s, a, ref = c2
+    say(f"c2 apply {prec}, nb=16")
+    L = Liouville(s, max_nb=16, precision=prec)
+    got = to_complex(L.apply(a))[:, ROWS]
+    L.close()
+    err = rel_err(got, ref)
+    say(f"  rows {ROWS}: rel err {err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-8, "rel1e-10"), ("fp32", 1e-5, "1meV")])
+def test_c2_davidson_vs_oracle_roots(systems, prec, tol, bar):
+    from paper_2309_03513_amd import Liouville
+    s = systems("c2")
+    ref = _golden()
+    say(f"c2 davidson {prec}: 8 roots, block 16")
+    L = Liouville(s, max_nb=16, precision=prec)
+    om, _, res, nit, st = L.davidson(8, 16, tol=tol, max_iter=100, want_x=False)
+    L.close()
+    d = np.abs(om - ref)
+    say(f"  iterations {nit}, status {st}, max |d omega| {d.max():.3e} Ha "
+        f"({d.max() / MEV:.4f} meV), max rel {np.max(d / ref):.3e}")
+    assert st == 0
+    if bar == "1meV":
+        assert d.max() <= MEV
+    else:
+        assert np.max(d / ref) <= 1e-10
