@@ -108,9 +108,18 @@ wtd_status wtd_apply_liouville(wtd_ctx *ctx, int32_t nb, const void *a, void *la
  * form the Davidson solver applies (Sec. 4).  Asynchronous.                     */
 wtd_status wtd_apply_transition(wtd_ctx *ctx, int32_t nb, const double *X, double *T);
 
-/* Gradients of E = sum Re(conj(g_la) la) with respect to the (re, im) parts of
- * a and of the occupied coefficients.  Not provided by this version: returns
- * WTD_ERR_UNIMPLEMENTED.                                                         */
+/* Gradients of E = sum Re(conj(g_la) la), la = L a, with respect to the
+ * (re, im) parts of a and of the occupied coefficients c_occ (the derivative of
+ * the excitation energy with respect to the orbitals that the Z-vector equation
+ * of the paper's Sec. 2.2, Eq. z-v-eq, is built from):
+ *   g_a   = W L (W^-1 g_la)  (W: half-sphere weights 1 at m = 0, 2 elsewhere)
+ *   g_occ = (2 - delta_m0) x coefficients of gamma_w(r), the derivative with
+ *           respect to phi_w(r) of the response and exchange terms; the
+ *           orbital-times-trial pair densities it needs are recomputed.
+ * a, g_la: device [nb][nocc][npw][2]; g_a: same or NULL; g_occ: device
+ * [nocc][npw][2] or NULL; all in the context precision; outputs are
+ * overwritten and must not alias the inputs.  nb <= min(max_nb, 16).
+ * Asynchronous.  Errors: WTD_ERR_ARG, WTD_ERR_SHAPE.                        */
 wtd_status wtd_apply_liouville_bwd(wtd_ctx *ctx, int32_t nb, const void *a, const void *g_la,
                                    void *g_a, void *g_occ);
 

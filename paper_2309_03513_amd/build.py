@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwtd.so")
-SOURCES = ["wtd_capi.hip", "wtd_transforms.hip", "wtd_gemm.hip", "wtd_davidson.hip"]
+SOURCES = ["wtd_capi.hip", "wtd_transforms.hip", "wtd_gemm.hip", "wtd_davidson.hip",
+           "wtd_contract.hip", "wtd_backward.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

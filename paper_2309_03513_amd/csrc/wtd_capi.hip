@@ -12,6 +12,7 @@
 //   8. Q = Phi_c^T r ; T = (eps_c - eps_v) S + Q ; la = Phi_c T
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -86,9 +87,19 @@ struct wtd_ctx {
   void* S = nullptr;         // [max_nb*nocc][nc]
   void* Q = nullptr;
   void* Tm = nullptr;
+  void* gemm_scratch = nullptr;  // split-K partial products
+  size_t gemm_scratch_elems = 0;
   int npairs = 0, npack_pairs = 0, pair_chunk = 0;
   int4* quads = nullptr;     // pair packs
   int4* hquads = nullptr;    // Hartree packs
+  // backward-only buffers, allocated on the first backward call
+  bool bwd_ready = false;
+  void* gt = nullptr;        // [max_nb][nocc][nr] cotangent fields g~
+  void* drhog = nullptr;     // [max_nb][nr]
+  void* vhg = nullptr;       // [max_nb][nr]
+  void* gamma = nullptr;     // [nocc][nr]
+  void* gbuf = nullptr;      // [max_nb][nocc][2 npw]
+  int4* pquads = nullptr;    // packs of stored pair fields (2p, 2p+1)
   int* pidx = nullptr;       // [nocc][nocc]
   wtd::Profiler prof;
 };
@@ -435,7 +446,11 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
   if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D)) c->tau = dalloc(c, (size_t)c->npairs * nr * sizeof(T));
   c->wst = dalloc(c, nwp * c->g.n0 * c->g.nw * sizeof(cplx<T>));
-  c->pair_chunk = std::max(1, std::min(c->npack_pairs, 512));
+  // packed pairs per Poisson batch; the density-stick intermediate of one batch
+  // is batch * n0 * n_d complex values (WTD_PAIR_CHUNK overrides the default)
+  int chunk = 512;
+  if (const char* e = std::getenv("WTD_PAIR_CHUNK")) chunk = std::max(1, std::atoi(e));
+  c->pair_chunk = std::max(1, std::min(c->npack_pairs, chunk));
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
   c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nd * sizeof(cplx<T>));
   c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
@@ -443,6 +458,8 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->S = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
   c->Q = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
   c->Tm = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
+  c->gemm_scratch_elems = (size_t)16 * mnb * nocc * nc;
+  c->gemm_scratch = dalloc(c, c->gemm_scratch_elems * sizeof(T));
 }
 
 template <typename T>
@@ -507,9 +524,12 @@ void apply_core(wtd_ctx* c, int nb) {
   }
   // 6. R
   prof_next(c, 6);
-  launch_contract<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau, c->pidx,
-                     (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
-                     (T)c->alpha, k1e, k1d, (T*)c->R, s);
+  if (!launch_contract_mfma<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau,
+                               (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
+                               (T)c->alpha, k1e, k1d, (T*)c->R, s))
+    launch_contract<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau, c->pidx,
+                       (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
+                       (T)c->alpha, k1e, k1d, (T*)c->R, s);
   // 7. back to the sphere
   prof_next(c, 7);
   launch_fields_to_wsticks<T>(g, (const T*)c->R, nb, nocc, nocc, (cplx<T>*)c->wst, s);
@@ -518,7 +538,8 @@ void apply_core(wtd_ctx* c, int nb) {
                            (T)(std::sqrt(g.omega) / (double)g.nr), (T*)c->rg, s);
   // 8a. Q = Phi_c^T r
   prof_next(c, 8);
-  launch_gemm<T, true>(F, nc, K, (const T*)c->rg, K, (const T*)c->c_condw, K, (T*)c->Q, nc, s);
+  launch_gemm<T, true>(F, nc, K, (const T*)c->rg, K, (const T*)c->c_condw, K, (T*)c->Q, nc, s,
+                       (T*)c->gemm_scratch, c->gemm_scratch_elems);
 }
 
 template <typename T>
@@ -527,7 +548,8 @@ void apply_impl(wtd_ctx* c, int nb, const T* a, T* la) {
   const int nocc = c->nocc, npw = c->npw, nc = c->nc;
   const int K = 2 * npw, F = nb * nocc;
   prof_mark(c, 0);
-  launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s);
+  launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s,
+                       (T*)c->gemm_scratch, c->gemm_scratch_elems);
   launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
   apply_core<T>(c, nb);
   prof_next(c, 8);
@@ -562,6 +584,109 @@ void apply_transition_any(wtd_ctx* c, int nb, const double* X, double* T) {
     apply_transition_impl<double>(c, nb, X, T);
   else
     apply_transition_impl<float>(c, nb, X, T);
+}
+
+// ---------------------------------------------------------------- backward
+template <typename T>
+void bwd_prepare(wtd_ctx* c) {
+  if (c->bwd_ready) return;
+  const int64_t nr = c->g.nr;
+  const int mnb = c->max_nb, nocc = c->nocc;
+  c->gt = dalloc(c, (size_t)mnb * nocc * nr * sizeof(T));
+  c->drhog = dalloc(c, (size_t)mnb * nr * sizeof(T));
+  c->vhg = dalloc(c, (size_t)mnb * nr * sizeof(T));
+  c->gamma = dalloc(c, (size_t)nocc * nr * sizeof(T));
+  c->gbuf = dalloc(c, (size_t)mnb * nocc * 2 * c->npw * sizeof(T));
+  std::vector<int4> q(c->npack_pairs);
+  for (int p = 0; p < c->npack_pairs; ++p)
+    q[p] = int4{2 * p, -1, (2 * p + 1 < c->npairs) ? 2 * p + 1 : -1, -1};
+  c->pquads = (int4*)dalloc(c, q.size() * sizeof(int4));
+  h2d(c, c->pquads, q.data(), q.size() * sizeof(int4));
+  c->bwd_ready = true;
+}
+
+// v_c * of nf fields held at src (packed two per complex transform) into out
+template <typename T>
+void hartree_fields(wtd_ctx* c, const T* src, int nf, T* out) {
+  const int nh = (nf + 1) / 2;
+  launch_pairs_to_dsticks<T>(c->g, src, c->hquads, nh, nf, (cplx<T>*)c->dst, c->stream);
+  launch_dstick_poisson<T>(c->g, (cplx<T>*)c->dst, nh, c->stream);
+  launch_dsticks_to_fields<T>(c->g, (const cplx<T>*)c->dst, nh, nf, out, c->stream);
+}
+
+template <typename T>
+void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
+  const Geometry& G = c->g;
+  hipStream_t s = c->stream;
+  const int nocc = c->nocc, npw = c->npw, nc = c->nc;
+  const int K = 2 * npw, F = nb * nocc;
+  bwd_prepare<T>(c);
+  if (g_a) {
+    // dE/da = W L (W^-1 g)
+    WTD_HIP(hipMemcpyAsync(c->gbuf, g, (size_t)F * K * sizeof(T), hipMemcpyDeviceToDevice, s));
+    launch_weights<T>((T*)c->gbuf, F, npw, 0, s);
+    apply_impl<T>(c, nb, (const T*)c->gbuf, g_a);
+    launch_weights<T>(g_a, F, npw, 1, s);
+  }
+  if (!g_occ) return;
+  const bool k1e = (c->mask & WTD_TERM_K1E) && c->ck != 0.0;
+  const bool k1d = (c->mask & WTD_TERM_K1D) && c->alpha != 0.0;
+  if (!k1e && !k1d) {
+    WTD_HIP(hipMemsetAsync(g_occ, 0, (size_t)nocc * K * sizeof(T), s));
+    return;
+  }
+  const T iso = (T)(1.0 / std::sqrt(G.omega));
+  // projected trial fields a~(r) and drho
+  launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s,
+                       (T*)c->gemm_scratch, c->gemm_scratch_elems);
+  launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
+  launch_sphere_to_wsticks<T>(G, (const T*)c->ag, F, npw, nb, nocc, (cplx<T>*)c->wst, s);
+  launch_wsticks_to_fields<T>(G, (const cplx<T>*)c->wst, nb, nocc, nocc, iso, (T*)c->at,
+                              (const T*)c->phi, k1e ? (T*)c->drho : nullptr, s);
+  // cotangent fields g~(r) = sum_c (phi_c . g) phi_c (Euclidean dot) and drho^g
+  launch_gemm<T, true>(F, nc, K, g, K, (const T*)c->c_cond, K, (T*)c->Q, nc, s,
+                       (T*)c->gemm_scratch, c->gemm_scratch_elems);
+  launch_gemm<T, false>(F, K, nc, (const T*)c->Q, nc, (const T*)c->c_cond, K, (T*)c->rg, K, s);
+  launch_sphere_to_wsticks<T>(G, (const T*)c->rg, F, npw, nb, nocc, (cplx<T>*)c->wst, s);
+  launch_wsticks_to_fields<T>(G, (const cplx<T>*)c->wst, nb, nocc, nocc, iso, (T*)c->gt,
+                              (const T*)c->phi, k1e ? (T*)c->drhog : nullptr, s);
+  // exchange part: P_wv' = M_wv' + M_v'w -> v_c * P -> gamma = -alpha sum_v' phi_v' (v_c * P)
+  if (k1d) {
+    launch_pair_density<T>(G, nb, nocc, (const T*)c->gt, (const T*)c->at, (T*)c->tau, s);
+    for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
+      const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
+      const int nf = std::min(2 * np, c->npairs - 2 * p0);
+      // pack p of this chunk holds stored pair fields 2 (p0 + p) and 2 (p0 + p) + 1
+      launch_pairs_to_dsticks<T>(G, (const T*)c->tau + (int64_t)2 * p0 * G.nr, c->pquads, np, nf,
+                                 (cplx<T>*)c->dst, s);
+      launch_dstick_poisson<T>(G, (cplx<T>*)c->dst, np, s);
+      launch_dsticks_to_fields<T>(G, (const cplx<T>*)c->dst, np, nf,
+                                  (T*)c->tau + (int64_t)2 * p0 * G.nr, s);
+    }
+    if (!launch_contract_mfma<T>(G, 1, nocc, (const T*)c->phi, (const T*)c->phi,
+                                 (const T*)c->tau, nullptr, nullptr, (const T*)c->fxc, (T)0,
+                                 (T)c->alpha, false, true, (T*)c->gamma, s))
+      launch_contract<T>(G, 1, nocc, (const T*)c->phi, (const T*)c->phi, (const T*)c->tau,
+                         c->pidx, nullptr, nullptr, (const T*)c->fxc, (T)0, (T)c->alpha, false,
+                         true, (T*)c->gamma, s);
+  } else {
+    WTD_HIP(hipMemsetAsync(c->gamma, 0, (size_t)nocc * G.nr * sizeof(T), s));
+  }
+  // response part
+  if (k1e) {
+    hartree_fields<T>(c, (const T*)c->drho, nb, (T*)c->vh);
+    hartree_fields<T>(c, (const T*)c->drhog, nb, (T*)c->vhg);
+    launch_gamma_k1e<T>(G, nb, nocc, (T)c->ck, (const T*)c->gt, (const T*)c->at,
+                        (const T*)c->vh, (const T*)c->drho, (const T*)c->vhg,
+                        (const T*)c->drhog, (const T*)c->fxc, (T*)c->gamma, s);
+  }
+  // dE/dc_w(m) = (2 - delta_m0) coefficients of gamma_w
+  const int npt = (nocc + 1) / 2;
+  launch_fields_to_wsticks<T>(G, (const T*)c->gamma, 1, nocc, nocc, (cplx<T>*)c->wst, s);
+  launch_wsticks_to_sphere<T>(G, (cplx<T>*)c->wst, npt, s);
+  launch_extract_sphere<T>(G, (const cplx<T>*)c->wst, 1, nocc, nocc, npw,
+                           (T)(std::sqrt(G.omega) / (double)G.nr), g_occ, s);
+  launch_weights<T>(g_occ, nocc, npw, 1, s);
 }
 
 // ---------------------------------------------------------------- Davidson (FP64)
@@ -847,14 +972,18 @@ wtd_status wtd_apply_transition(wtd_ctx* ctx, int32_t nb, const double* X, doubl
 
 wtd_status wtd_apply_liouville_bwd(wtd_ctx* ctx, int32_t nb, const void* a, const void* g_la,
                                    void* g_a, void* g_occ) {
-  (void)nb;
-  (void)a;
-  (void)g_la;
-  (void)g_a;
-  (void)g_occ;
   return guarded([&]() -> wtd_status {
-    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
-    throw StatusError{WTD_ERR_UNIMPLEMENTED, "wtd_apply_liouville_bwd is not provided yet"};
+    WTD_REQUIRE(ctx && a && g_la, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
+    WTD_REQUIRE(nb <= 16, WTD_ERR_SHAPE, "the backward apply takes at most 16 trials per call");
+    WTD_REQUIRE(g_a != a && g_a != g_la && g_occ != a && g_occ != g_la, WTD_ERR_ARG,
+                "outputs must not alias the inputs");
+    if (ctx->prec == WTD_FP64)
+      bwd_impl<double>(ctx, nb, (const double*)a, (const double*)g_la, (double*)g_a,
+                       (double*)g_occ);
+    else
+      bwd_impl<float>(ctx, nb, (const float*)a, (const float*)g_la, (float*)g_a, (float*)g_occ);
+    return WTD_OK;
   });
 }
 

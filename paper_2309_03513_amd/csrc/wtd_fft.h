@@ -133,6 +133,39 @@ __device__ __forceinline__ void dft8(cplx<T>* v) {
   }
 }
 
+// 9-point DFT as 3 x 3: DFT3 over n1 of x[3 n1 + n2], twiddles w9^(n2 k1),
+// DFT3 over n2; output index k1 + 3 k2.
+template <int S, typename T>
+__device__ __forceinline__ void dft9(cplx<T>* v) {
+  const T c1 = T(0.76604444311897803520239265055542);   // cos(2 pi/9)
+  const T s1 = T(0.64278760968653932632264340990726);   // sin(2 pi/9)
+  const T c2 = T(0.17364817766693034885171662676931);   // cos(4 pi/9)
+  const T s2 = T(0.98480775301220805936674302458952);   // sin(4 pi/9)
+  const T c4 = T(-0.93969262078590838405410927732473);  // cos(8 pi/9)
+  const T s4 = T(0.34202014332566873304409961468226);   // sin(8 pi/9)
+  cplx<T> y0[3] = {v[0], v[3], v[6]};
+  cplx<T> y1[3] = {v[1], v[4], v[7]};
+  cplx<T> y2[3] = {v[2], v[5], v[8]};
+  dft3<S>(y0);
+  dft3<S>(y1);
+  dft3<S>(y2);
+  auto rot = [](cplx<T> z, T c, T s) -> cplx<T> {
+    return {z.x * c - T(S) * z.y * s, z.y * c + T(S) * z.x * s};
+  };
+  y1[1] = rot(y1[1], c1, s1);
+  y1[2] = rot(y1[2], c2, s2);
+  y2[1] = rot(y2[1], c2, s2);
+  y2[2] = rot(y2[2], c4, s4);
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    cplx<T> z[3] = {y0[k1], y1[k1], y2[k1]};
+    dft3<S>(z);
+    v[k1] = z[0];
+    v[k1 + 3] = z[1];
+    v[k1 + 6] = z[2];
+  }
+}
+
 template <int S, typename T>
 __device__ __forceinline__ void dft_r(int r, cplx<T>* v) {
   switch (r) {

@@ -7,11 +7,11 @@
 // 16-deep K slices staged in LDS; each wave owns a 32x32 quadrant computed as
 // 2x2 blocks of v_mfma_{f64,f32}_16x16x4.
 //
-// MFMA 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16].  Accumulator register i of lane l holds
-// D[4 (l / 16) + i][l % 16] for the f32 instruction and D[l / 16 + 4 i][l % 16]
-// for the f64 one (checked against numpy by the GEMM unit test).
+// Operand layouts: see wtd_mfma.h.
 #include "wtd_internal.h"
+#include "wtd_mfma.h"
+
+#include <algorithm>
 
 namespace wtd {
 
@@ -19,35 +19,13 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16;
 
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Acc;
-template <>
-struct Acc<double> {
-  typedef d4_t type;
-  static __device__ __forceinline__ type mfma(double a, double b, type c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int i) { return (lane >> 4) + 4 * i; }
-};
-template <>
-struct Acc<float> {
-  typedef f4_t type;
-  static __device__ __forceinline__ type mfma(float a, float b, type c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
-};
-
 template <typename T, bool B_KMAJOR>
 __global__ void __launch_bounds__(256)
-k_gemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restrict__ B, int ldb,
-       T* __restrict__ C, int ldc) {
+k_gemm(int M, int N, int K, int kchunk, const T* __restrict__ A, int lda,
+       const T* __restrict__ B, int ldb, T* __restrict__ C, int ldc, int64_t zstride) {
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
-  typedef typename Acc<T>::type acc_t;
+  typedef typename Mfma<T>::acc_t acc_t;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -58,14 +36,18 @@ k_gemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restric
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  // split-K: slice z covers [kbeg, kend) and writes its own partial result
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  C += (int64_t)blockIdx.z * zstride;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     {  // A tile: row = tid / 4, four consecutive k
       const int row = tid >> 2, kq = (tid & 3) * 4;
       const int gm = m0 + row;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gk = k0 + kq + i;
-        As[kq + i][row] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : T(0);
+        As[kq + i][row] = (gm < M && gk < kend) ? A[(int64_t)gm * lda + gk] : T(0);
       }
     }
     if (B_KMAJOR) {
@@ -74,7 +56,7 @@ k_gemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restric
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gk = k0 + kq + i;
-        Bs[kq + i][col] = (gn < N && gk < K) ? B[(int64_t)gn * ldb + gk] : T(0);
+        Bs[kq + i][col] = (gn < N && gk < kend) ? B[(int64_t)gn * ldb + gk] : T(0);
       }
     } else {
       const int kk = tid >> 4, nq = (tid & 15) * 4;
@@ -82,7 +64,7 @@ k_gemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restric
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int gn = n0 + nq + i;
-        Bs[kk][nq + i] = (gn < N && gk < K) ? B[(int64_t)gk * ldb + gn] : T(0);
+        Bs[kk][nq + i] = (gn < N && gk < kend) ? B[(int64_t)gk * ldb + gn] : T(0);
       }
     }
     __syncthreads();
@@ -96,7 +78,7 @@ k_gemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restric
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = Acc<T>::mfma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::run(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
@@ -107,32 +89,63 @@ k_gemm(int M, int N, int K, const T* __restrict__ A, int lda, const T* __restric
       const int gn = n0 + wn * 32 + j * 16 + (lane & 15);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wm * 32 + i * 16 + Acc<T>::row(lane, e);
+        const int gm = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, e);
         if (gm < M && gn < N) C[(int64_t)gm * ldc + gn] = acc[i][j][e];
       }
     }
+}
+
+// C[m][n] = sum_z P[z][m][n] (fixed order: deterministic)
+template <typename T>
+__global__ void k_sum_splits(const T* __restrict__ P, int nz, int M, int N, T* __restrict__ C,
+                             int ldc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * N) return;
+  const int m = (int)(i / N), n = (int)(i % N);
+  T acc = T(0);
+  for (int z = 0; z < nz; ++z) acc += P[(int64_t)z * M * N + i];
+  C[(int64_t)m * ldc + n] = acc;
 }
 
 }  // namespace
 
 template <typename T, bool B_KMAJOR>
 void launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
-                 hipStream_t s) {
+                 hipStream_t s, T* scratch, size_t scratch_elems) {
   if (M <= 0 || N <= 0) return;
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, 1);
   WTD_REQUIRE(grid.y < 65536, WTD_ERR_SHAPE, "GEMM M too large");
-  hipLaunchKernelGGL((k_gemm<T, B_KMAJOR>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
-                     ldc);
+  // few output tiles and a long K: split K over up to 16 slices into scratch
+  int nz = 1;
+  const int tiles = (int)(grid.x * grid.y);
+  if (scratch && tiles < 512 && K >= 8 * BK) {
+    nz = std::min(16, std::max(1, 1024 / tiles));
+    nz = std::min(nz, (K + 4 * BK - 1) / (4 * BK));
+    while (nz > 1 && (size_t)nz * M * N > scratch_elems) --nz;
+  }
+  if (nz == 1) {
+    hipLaunchKernelGGL((k_gemm<T, B_KMAJOR>), grid, dim3(256), 0, s, M, N, K, K, A, lda, B, ldb,
+                       C, ldc, (int64_t)0);
+  } else {
+    const int kchunk = ((K + nz - 1) / nz + BK - 1) / BK * BK;
+    nz = (K + kchunk - 1) / kchunk;
+    grid.z = nz;
+    hipLaunchKernelGGL((k_gemm<T, B_KMAJOR>), grid, dim3(256), 0, s, M, N, K, kchunk, A, lda, B,
+                       ldb, scratch, N, (int64_t)M * N);
+    const int64_t tot = (int64_t)M * N;
+    hipLaunchKernelGGL(k_sum_splits<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       scratch, nz, M, N, C, ldc);
+  }
   WTD_HIP(hipGetLastError());
 }
 
 template void launch_gemm<double, true>(int, int, int, const double*, int, const double*, int,
-                                        double*, int, hipStream_t);
+                                        double*, int, hipStream_t, double*, size_t);
 template void launch_gemm<double, false>(int, int, int, const double*, int, const double*, int,
-                                         double*, int, hipStream_t);
+                                         double*, int, hipStream_t, double*, size_t);
 template void launch_gemm<float, true>(int, int, int, const float*, int, const float*, int,
-                                       float*, int, hipStream_t);
+                                       float*, int, hipStream_t, float*, size_t);
 template void launch_gemm<float, false>(int, int, int, const float*, int, const float*, int,
-                                        float*, int, hipStream_t);
+                                        float*, int, hipStream_t, float*, size_t);
 
 }  // namespace wtd

@@ -88,11 +88,31 @@ void launch_contract(const Geometry& g, int nb, int nocc, const T* phi, const T*
                      const T* tau, const int* pair_index, const T* vh, const T* drho,
                      const T* fxc, T ck, T alpha, bool k1e, bool k1d, T* R, hipStream_t s);
 
+// MFMA contraction for Nocc <= 128 (wtd_contract.hip); returns false if not applicable.
+template <typename T>
+bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
+                          const T* tau, const T* vh, const T* drho, const T* fxc, T ck, T alpha,
+                          bool k1e, bool k1d, T* R, hipStream_t s);
+
+// Backward kernels (wtd_backward.hip).
+template <typename T>
+void launch_pair_density(const Geometry& g, int nb, int nocc, const T* X, const T* Y, T* P,
+                         hipStream_t s);
+template <typename T>
+void launch_gamma_k1e(const Geometry& g, int nb, int nocc, T ck, const T* gt, const T* at,
+                      const T* vh, const T* drho, const T* vhg, const T* drhog, const T* fxc,
+                      T* gamma, hipStream_t s);
+// mode 0: divide by the half-sphere weights, mode 1: multiply; Im at m = 0 zeroed
+template <typename T>
+void launch_weights(T* x, int64_t nf, int npw, int mode, hipStream_t s);
+
 // GEMMs (wtd_gemm.hip).  C[m][n] = sum_k A[m*lda + k] * B(k, n), with
 // B(k, n) = B[n*ldb + k] (B_KMAJOR) or B[k*ldb + n].
+// With a scratch buffer, short-and-wide problems split K into slices whose
+// partial products are summed in a fixed order.
 template <typename T, bool B_KMAJOR>
 void launch_gemm(int M, int N, int K, const T* A, int lda, const T* B, int ldb, T* C, int ldc,
-                 hipStream_t s);
+                 hipStream_t s, T* scratch = nullptr, size_t scratch_elems = 0);
 
 // Small elementwise kernels (wtd_transforms.hip)
 template <typename T>

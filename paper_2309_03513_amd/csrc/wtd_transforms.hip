@@ -14,6 +14,7 @@
 // and a plane pass (2D FFT over (i1, i2) at fixed i0, staged in LDS).  Two real
 // fields travel as the real and imaginary parts of one complex field (the
 // Gamma-point packing).  Stick data layout: [pack][i0 or k0][stick].
+#include "wtd_fft_ct.h"
 #include "wtd_internal.h"
 
 namespace wtd {
@@ -48,24 +49,51 @@ int pick_maxb(int nlines, const FFTPlan& p, int nthreads) {
   }
 
 // 2D FFT of the LDS plane [k1][k2] (k2 fastest): S = -1 rows first then columns
-// (forward), S = +1 columns first then rows (inverse).  Either order gives the
-// same 2D transform; the order only matters for future pruning.
-template <int S, int MB1, int MB2, typename T>
+// (forward), S = +1 columns first then rows (inverse).  SN > 0: n1 = n2 = SN with
+// a compile-time plan and the twiddle table `twl` in LDS; SN = 0: runtime plans.
+template <int S, int SN, int MB1, int MB2, typename T>
 __device__ __forceinline__ void plane_fft(cplx<T>* pl, const FFTPlan& P1, const FFTPlan& P2,
                                           int n1, int n2, const cplx<T>* tw1,
-                                          const cplx<T>* tw2) {
-  if (S < 0) {
-    lds_fft<S, MB2, false>(pl, P2, n1, 1, n2, tw2);   // along i2: n1 rows
-    lds_fft<S, MB1, true>(pl, P1, n2, n2, 1, tw1);    // along i1: n2 columns
+                                          const cplx<T>* tw2, const cplx<T>* twl) {
+  if constexpr (SN > 0) {
+    if (S < 0) {
+      ct_fft<S, SN, SN, 1, SN, kPlaneThreads, false>(pl, twl);
+      ct_fft<S, SN, SN, SN, 1, kPlaneThreads, true>(pl, twl);
+    } else {
+      ct_fft<S, SN, SN, SN, 1, kPlaneThreads, true>(pl, twl);
+      ct_fft<S, SN, SN, 1, SN, kPlaneThreads, false>(pl, twl);
+    }
   } else {
-    lds_fft<S, MB1, true>(pl, P1, n2, n2, 1, tw1);
-    lds_fft<S, MB2, false>(pl, P2, n1, 1, n2, tw2);
+    if (S < 0) {
+      lds_fft<S, MB2, false>(pl, P2, n1, 1, n2, tw2);   // along i2: n1 rows
+      lds_fft<S, MB1, true>(pl, P1, n2, n2, 1, tw1);    // along i1: n2 columns
+    } else {
+      lds_fft<S, MB1, true>(pl, P1, n2, n2, 1, tw1);
+      lds_fft<S, MB2, false>(pl, P2, n1, 1, n2, tw2);
+    }
   }
+}
+
+// 1D FFTs along i0 of kStickTile sticks held as [i0][stick] in LDS.
+template <int S, int SN, int MB, typename T>
+__device__ __forceinline__ void stick_fft(cplx<T>* buf, const FFTPlan& P0, const cplx<T>* tw0,
+                                          const cplx<T>* twl) {
+  if constexpr (SN > 0)
+    ct_fft<S, SN, kStickTile, kStickTile, 1, kStickThreads, true>(buf, twl);
+  else
+    lds_fft<S, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+}
+
+// copy an N-entry twiddle table into LDS (callers synchronise before use)
+template <int SN, typename T>
+__device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) {
+  if constexpr (SN > 0)
+    for (int i = threadIdx.x; i < SN; i += blockDim.x) twl[i] = tw[i];
 }
 
 // ---------------------------------------------------------------- sphere -> sticks
 // coef: [nb][per_trial][npw][2]; pack (b, j) carries fields v = 2j (re) and 2j+1 (im).
-template <int MB, typename T>
+template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
 k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw, int n0, int nw,
                     const int* __restrict__ off, const int4* __restrict__ ent, FFTPlan P0,
@@ -79,6 +107,8 @@ k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw,
   const T* c1 = coef + ((int64_t)b * per_trial + v1) * npw * 2;
   const T* c2 = (v2 < per_trial) ? c1 + (int64_t)npw * 2 : nullptr;
   const int tot = n0 * kStickTile;
+  cplx<T>* twl = buf + tot;
+  stage_twiddles<SN>(twl, tw0);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) buf[i] = {T(0), T(0)};
   __syncthreads();
   for (int e = off[tile] + threadIdx.x; e < off[tile + 1]; e += blockDim.x) {
@@ -97,7 +127,7 @@ k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw,
     buf[q.w * kStickTile + q.z] = z;
   }
   __syncthreads();
-  lds_fft<+1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  stick_fft<+1, SN, MB>(buf, P0, tw0, twl);
   cplx<T>* out = wst + (int64_t)pack * n0 * nw;
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
@@ -109,7 +139,7 @@ k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw,
 // ---------------------------------------------------------------- sticks -> real fields
 // One workgroup per (i0, trial b); loops over the packs of that trial.  With
 // drho != nullptr also forms drho_b = sum_v phi_v out_bv on the plane.
-template <int MB1, int MB2, typename T>
+template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int n0, int n1,
                     int n2, int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
@@ -119,6 +149,8 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   T* acc = reinterpret_cast<T*>(pl + plane);
+  cplx<T>* twl = reinterpret_cast<cplx<T>*>(acc + (drho ? plane : 0));
+  stage_twiddles<SN>(twl, tw1);
   const int i0 = blockIdx.x;
   const int b = blockIdx.y;
   const int64_t nr = (int64_t)n0 * plane;
@@ -132,7 +164,7 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
     const cplx<T>* src = wst + ((int64_t)pack * n0 + i0) * nw;
     for (int s = threadIdx.x; s < nw; s += blockDim.x) pl[k12[s]] = src[s];
     __syncthreads();
-    plane_fft<+1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+    plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
     const int v1 = 2 * j, v2 = 2 * j + 1;
     T* o1 = out + ((int64_t)b * per_trial + v1) * nr + poff;
     T* o2 = o1 + nr;
@@ -159,7 +191,7 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
 // ---------------------------------------------------------------- pair products -> density sticks
 // quad (a, b, c, d): re = src[a]*src[b] (or src[a] if b < 0), im likewise from (c, d);
 // c < 0 means no imaginary part.
-template <int MB1, int MB2, typename T>
+template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, int limit, int n0,
                    int n1, int n2, int nd, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
@@ -168,6 +200,8 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
   extern __shared__ unsigned char smem_raw[];
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* twl = pl + plane;
+  stage_twiddles<SN>(twl, tw1);
   const int i0 = blockIdx.x;
   const int pack = blockIdx.y;
   const int64_t nr = (int64_t)n0 * plane;
@@ -184,7 +218,7 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
     pl[i] = {re, im};
   }
   __syncthreads();
-  plane_fft<-1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+  plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
   cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nd;
   for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
 }
@@ -192,7 +226,7 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
 // ---------------------------------------------------------------- Poisson on density sticks
 // forward FFT along i0, multiply by the kernel 4 pi/|G|^2 / N_r (v_g0/N_r at G = 0),
 // inverse FFT along i0; in place.
-template <int MB, typename T>
+template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
 k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict__ kern,
                  FFTPlan P0, const cplx<T>* __restrict__ tw0) {
@@ -202,13 +236,15 @@ k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict_
   const int pack = blockIdx.y;
   cplx<T>* base = dst + (int64_t)pack * n0 * nd;
   const int tot = n0 * kStickTile;
+  cplx<T>* twl = buf + tot;
+  stage_twiddles<SN>(twl, tw0);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
     buf[i] = (s < nd) ? base[(int64_t)i0 * nd + s] : cplx<T>{T(0), T(0)};
   }
   __syncthreads();
-  lds_fft<-1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  stick_fft<-1, SN, MB>(buf, P0, tw0, twl);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int k0 = i / kStickTile, l = i - k0 * kStickTile;
     const int s = tile * kStickTile + l;
@@ -216,7 +252,7 @@ k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict_
     buf[i] = cscale(buf[i], kv);
   }
   __syncthreads();
-  lds_fft<+1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  stick_fft<+1, SN, MB>(buf, P0, tw0, twl);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
@@ -225,7 +261,7 @@ k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict_
 }
 
 // ---------------------------------------------------------------- density sticks -> real fields
-template <int MB1, int MB2, typename T>
+template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1, int n2, int nd,
                     const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
@@ -234,6 +270,8 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
   extern __shared__ unsigned char smem_raw[];
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* twl = pl + plane;
+  stage_twiddles<SN>(twl, tw1);
   const int i0 = blockIdx.x;
   const int pack = blockIdx.y;
   const int64_t nr = (int64_t)n0 * plane;
@@ -242,7 +280,7 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
   const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nd;
   for (int s = threadIdx.x; s < nd; s += blockDim.x) pl[k12[s]] = src[s];
   __syncthreads();
-  plane_fft<+1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+  plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
   T* o1 = out + (int64_t)(2 * pack) * nr + (int64_t)i0 * plane;
   T* o2 = o1 + nr;
   const bool has2 = 2 * pack + 1 < nfield;
@@ -254,7 +292,7 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
 }
 
 // ---------------------------------------------------------------- real fields -> wave sticks
-template <int MB1, int MB2, typename T>
+template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int n0, int n1, int n2,
                     int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
@@ -270,15 +308,17 @@ k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int n0
   const int64_t nr = (int64_t)n0 * plane;
   const T* f1 = fields + ((int64_t)b * per_trial + v1) * nr + (int64_t)i0 * plane;
   const T* f2 = (v2 < per_trial) ? f1 + nr : nullptr;
+  cplx<T>* twl = pl + plane;
+  stage_twiddles<SN>(twl, tw1);
   for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {f1[i], f2 ? f2[i] : T(0)};
   __syncthreads();
-  plane_fft<-1, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2);
+  plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
   cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nw;
   for (int s = threadIdx.x; s < nw; s += blockDim.x) o[s] = pl[k12[s]];
 }
 
 // ---------------------------------------------------------------- wave sticks: forward along i0
-template <int MB, typename T>
+template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
 k_wsticks_forward(cplx<T>* __restrict__ wst, int n0, int nw, FFTPlan P0,
                   const cplx<T>* __restrict__ tw0) {
@@ -288,13 +328,15 @@ k_wsticks_forward(cplx<T>* __restrict__ wst, int n0, int nw, FFTPlan P0,
   const int pack = blockIdx.y;
   cplx<T>* base = wst + (int64_t)pack * n0 * nw;
   const int tot = n0 * kStickTile;
+  cplx<T>* twl = buf + tot;
+  stage_twiddles<SN>(twl, tw0);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
     buf[i] = (s < nw) ? base[(int64_t)i0 * nw + s] : cplx<T>{T(0), T(0)};
   }
   __syncthreads();
-  lds_fft<-1, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
+  stick_fft<-1, SN, MB>(buf, P0, tw0, twl);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int k0 = i / kStickTile, l = i - k0 * kStickTile;
     const int s = tile * kStickTile + l;
@@ -469,6 +511,67 @@ void check_lds(size_t bytes) {
 }  // namespace
 
 // ============================================================================ launchers
+// Grid sizes with compile-time FFT plans; other sizes use the runtime plans.
+int static_size(int n) { return (n == 72 || n == 108) ? n : 0; }
+int plane_static(const Geometry& g) { return g.n1 == g.n2 ? static_size(g.n1) : 0; }
+
+// Launch a stick kernel K<MB, SN, T> with the right static size or radix bound.
+#define WTD_STICK_LAUNCH(K, T, grid, lds0, stream, ...)                                     \
+  do {                                                                                      \
+    const int sn_ = static_size(g.n0);                                                      \
+    if (sn_ == 72) {                                                                        \
+      const size_t l_ = (lds0) + 72 * sizeof(cplx<T>);                                      \
+      set_lds((K<1, 72, T>), l_);                                                           \
+      hipLaunchKernelGGL((K<1, 72, T>), grid, dim3(kStickThreads), l_, stream, __VA_ARGS__); \
+    } else if (sn_ == 108) {                                                                \
+      const size_t l_ = (lds0) + 108 * sizeof(cplx<T>);                                     \
+      set_lds((K<1, 108, T>), l_);                                                          \
+      hipLaunchKernelGGL((K<1, 108, T>), grid, dim3(kStickThreads), l_, stream,             \
+                         __VA_ARGS__);                                                      \
+    } else {                                                                                \
+      const int mb_ = pick_maxb(kStickTile, g.plan0, kStickThreads);                        \
+      WTD_MAXB_DISPATCH(mb_, {                                                              \
+        set_lds((K<MB, 0, T>), (lds0));                                                     \
+        hipLaunchKernelGGL((K<MB, 0, T>), grid, dim3(kStickThreads), (lds0), stream,        \
+                           __VA_ARGS__);                                                    \
+      });                                                                                   \
+    }                                                                                       \
+    WTD_HIP(hipGetLastError());                                                             \
+  } while (0)
+
+// Launch a plane kernel K<MB1, MB2, SN, T>.
+#define WTD_PLANE_LAUNCH(K, T, grid, lds0, stream, ...)                                      \
+  do {                                                                                       \
+    const int sn_ = plane_static(g);                                                         \
+    if (sn_ == 72) {                                                                         \
+      const size_t l_ = (lds0) + 72 * sizeof(cplx<T>);                                       \
+      check_lds(l_);                                                                         \
+      set_lds((K<1, 1, 72, T>), l_);                                                         \
+      hipLaunchKernelGGL((K<1, 1, 72, T>), grid, dim3(kPlaneThreads), l_, stream,            \
+                         __VA_ARGS__);                                                       \
+    } else if (sn_ == 108) {                                                                 \
+      const size_t l_ = (lds0) + 108 * sizeof(cplx<T>);                                      \
+      check_lds(l_);                                                                         \
+      set_lds((K<1, 1, 108, T>), l_);                                                        \
+      hipLaunchKernelGGL((K<1, 1, 108, T>), grid, dim3(kPlaneThreads), l_, stream,           \
+                         __VA_ARGS__);                                                       \
+    } else {                                                                                 \
+      check_lds(lds0);                                                                       \
+      const int mb1_ = pick_maxb(g.n2, g.plan1, kPlaneThreads);                              \
+      const int mb2_ = pick_maxb(g.n1, g.plan2, kPlaneThreads);                              \
+      WTD_MAXB_DISPATCH(mb1_, {                                                              \
+        constexpr int M1 = MB;                                                               \
+        WTD_MAXB_DISPATCH(mb2_, {                                                            \
+          constexpr int M2 = MB;                                                             \
+          set_lds((K<M1, M2, 0, T>), (lds0));                                                \
+          hipLaunchKernelGGL((K<M1, M2, 0, T>), grid, dim3(kPlaneThreads), (lds0), stream,   \
+                             __VA_ARGS__);                                                   \
+        });                                                                                  \
+      });                                                                                    \
+    }                                                                                        \
+    WTD_HIP(hipGetLastError());                                                              \
+  } while (0)
+
 template <typename T>
 void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
                               int per_trial, cplx<T>* wst, hipStream_t s) {
@@ -476,21 +579,9 @@ void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int 
   const int npt = (per_trial + 1) / 2;
   dim3 grid(g.nwtile, nb * npt);
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
-  const int mb = pick_maxb(kStickTile, g.plan0, kStickThreads);
-  WTD_MAXB_DISPATCH(mb, {
-    set_lds((k_sphere_to_wsticks<MB, T>), lds);
-    hipLaunchKernelGGL((k_sphere_to_wsticks<MB, T>), grid, dim3(kStickThreads), lds, s, coef, per_trial, npt, npw, g.n0,
-                       g.nw, g.wtile_off, g.wtile_ent, g.plan0,
-                       static_cast<const cplx<T>*>(g.tw0), wst);
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_STICK_LAUNCH(k_sphere_to_wsticks, T, grid, lds, s, coef, per_trial, npt, npw, g.n0, g.nw,
+                   g.wtile_off, g.wtile_ent, g.plan0, static_cast<const cplx<T>*>(g.tw0), wst);
 }
-
-#define WTD_PLANE_DISPATCH(mb1, mb2, ...)                                    \
-  WTD_MAXB_DISPATCH(mb1, {                                                   \
-    constexpr int M1 = MB;                                                   \
-    WTD_MAXB_DISPATCH(mb2, { constexpr int M2 = MB; __VA_ARGS__; });         \
-  })
 
 template <typename T>
 void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
@@ -500,17 +591,9 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   const int npt = (per_trial + 1) / 2;
   dim3 grid(g.n0, nb);
   const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
-  check_lds(lds);
-  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
-  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
-  WTD_PLANE_DISPATCH(mb1, mb2, {
-    set_lds((k_wsticks_to_fields<M1, M2, T>), lds);
-    hipLaunchKernelGGL((k_wsticks_to_fields<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, wst, npt, per_trial, g.n0, g.n1,
-                       g.n2, g.nw, g.wst_k12, g.plan1, g.plan2,
-                       static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2),
-                       scale, out, phi, drho);
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_PLANE_LAUNCH(k_wsticks_to_fields, T, grid, lds, s, wst, npt, per_trial, g.n0, g.n1, g.n2,
+                   g.nw, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   static_cast<const cplx<T>*>(g.tw2), scale, out, phi, drho);
 }
 
 template <typename T>
@@ -518,30 +601,17 @@ void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads,
                              int limit, cplx<T>* dst, hipStream_t s) {
   dim3 grid(g.n0, npack);
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
-  check_lds(lds);
-  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
-  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
-  WTD_PLANE_DISPATCH(mb1, mb2, {
-    set_lds((k_pairs_to_dsticks<M1, M2, T>), lds);
-    hipLaunchKernelGGL((k_pairs_to_dsticks<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, src, quads, limit, g.n0, g.n1, g.n2, g.nd,
-                       g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
-                       static_cast<const cplx<T>*>(g.tw2), dst);
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_PLANE_LAUNCH(k_pairs_to_dsticks, T, grid, lds, s, src, quads, limit, g.n0, g.n1, g.n2, g.nd,
+                   g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   static_cast<const cplx<T>*>(g.tw2), dst);
 }
 
 template <typename T>
 void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s) {
   dim3 grid((g.nd + kStickTile - 1) / kStickTile, npack);
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
-  const int mb = pick_maxb(kStickTile, g.plan0, kStickThreads);
-  WTD_MAXB_DISPATCH(mb, {
-    set_lds((k_dstick_poisson<MB, T>), lds);
-    hipLaunchKernelGGL((k_dstick_poisson<MB, T>), grid, dim3(kStickThreads), lds, s, dst, g.n0, g.nd,
-                       static_cast<const T*>(g.dkern), g.plan0,
-                       static_cast<const cplx<T>*>(g.tw0));
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_STICK_LAUNCH(k_dstick_poisson, T, grid, lds, s, dst, g.n0, g.nd,
+                   static_cast<const T*>(g.dkern), g.plan0, static_cast<const cplx<T>*>(g.tw0));
 }
 
 template <typename T>
@@ -549,16 +619,9 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
                               T* out, hipStream_t s) {
   dim3 grid(g.n0, npack);
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
-  check_lds(lds);
-  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
-  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
-  WTD_PLANE_DISPATCH(mb1, mb2, {
-    set_lds((k_dsticks_to_fields<M1, M2, T>), lds);
-    hipLaunchKernelGGL((k_dsticks_to_fields<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, dst, nfield, g.n0, g.n1, g.n2, g.nd,
-                       g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
-                       static_cast<const cplx<T>*>(g.tw2), out);
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_PLANE_LAUNCH(k_dsticks_to_fields, T, grid, lds, s, dst, nfield, g.n0, g.n1, g.n2, g.nd,
+                   g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   static_cast<const cplx<T>*>(g.tw2), out);
 }
 
 template <typename T>
@@ -568,30 +631,17 @@ void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int pe
   const int npt = (per_trial + 1) / 2;
   dim3 grid(g.n0, nb * npt);
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
-  check_lds(lds);
-  const int mb1 = pick_maxb(g.n2, g.plan1, kPlaneThreads);
-  const int mb2 = pick_maxb(g.n1, g.plan2, kPlaneThreads);
-  WTD_PLANE_DISPATCH(mb1, mb2, {
-    set_lds((k_fields_to_wsticks<M1, M2, T>), lds);
-    hipLaunchKernelGGL((k_fields_to_wsticks<M1, M2, T>), grid, dim3(kPlaneThreads), lds, s, fields, npt, per_trial, g.n0, g.n1,
-                       g.n2, g.nw, g.wst_k12, g.plan1, g.plan2,
-                       static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2),
-                       wst);
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_PLANE_LAUNCH(k_fields_to_wsticks, T, grid, lds, s, fields, npt, per_trial, g.n0, g.n1, g.n2,
+                   g.nw, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   static_cast<const cplx<T>*>(g.tw2), wst);
 }
 
 template <typename T>
 void launch_wsticks_to_sphere(const Geometry& g, cplx<T>* wst, int npack, hipStream_t s) {
   dim3 grid((g.nw + kStickTile - 1) / kStickTile, npack);
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
-  const int mb = pick_maxb(kStickTile, g.plan0, kStickThreads);
-  WTD_MAXB_DISPATCH(mb, {
-    set_lds((k_wsticks_forward<MB, T>), lds);
-    hipLaunchKernelGGL((k_wsticks_forward<MB, T>), grid, dim3(kStickThreads), lds, s, wst, g.n0, g.nw, g.plan0,
-                       static_cast<const cplx<T>*>(g.tw0));
-  });
-  WTD_HIP(hipGetLastError());
+  WTD_STICK_LAUNCH(k_wsticks_forward, T, grid, lds, s, wst, g.n0, g.nw, g.plan0,
+                   static_cast<const cplx<T>*>(g.tw0));
 }
 
 template <typename T>
