@@ -79,6 +79,7 @@ struct wtd_ctx {
   void* R = nullptr;         // [max_nb][nocc][nr]
   void* drho = nullptr;      // [max_nb][nr]
   void* vh = nullptr;        // [max_nb][nr]
+  void* drho_part = nullptr; // [kDrhoGroups][max_nb][nr] partial densities
   void* tau = nullptr;       // [npairs][nr]
   void* wst = nullptr;       // [max packs][n0][nw] complex
   void* dst = nullptr;       // [pair chunk][n0][nd] complex
@@ -107,6 +108,9 @@ struct wtd_ctx {
 namespace wtd {
 
 namespace {
+
+// groups over which the orbital loop of the trial transform is split
+constexpr int kDrhoGroups = 8;
 
 void* dalloc(wtd_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 16;
@@ -444,6 +448,7 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->R = dalloc(c, (size_t)mnb * nocc * nr * sizeof(T));
   c->drho = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
+  c->drho_part = dalloc(c, (size_t)kDrhoGroups * mnb * nr * sizeof(T));
   if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D)) c->tau = dalloc(c, (size_t)c->npairs * nr * sizeof(T));
   c->wst = dalloc(c, nwp * c->g.n0 * c->g.nw * sizeof(cplx<T>));
   // packed pairs per Poisson batch; the density-stick intermediate of one batch
@@ -498,7 +503,7 @@ void apply_core(wtd_ctx* c, int nb) {
   launch_sphere_to_wsticks<T>(g, (const T*)c->ag, F, npw, nb, nocc, (cplx<T>*)c->wst, s);
   launch_wsticks_to_fields<T>(g, (const cplx<T>*)c->wst, nb, nocc, nocc,
                               (T)(1.0 / std::sqrt(g.omega)), (T*)c->at, (const T*)c->phi,
-                              k1e ? (T*)c->drho : nullptr, s);
+                              k1e ? (T*)c->drho : nullptr, s, (T*)c->drho_part, kDrhoGroups);
   // 4. Hartree potential of drho_b
   if (k1e) {
     prof_next(c, 2);

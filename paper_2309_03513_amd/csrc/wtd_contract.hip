@@ -127,6 +127,55 @@ __device__ __forceinline__ void load_tau_full(T* s, const T* __restrict__ tau, i
   }
 }
 
+// Register-staged variants used for prefetching: fetch_* issue the global
+// loads of a tile into registers, put_* store them into the LDS tile.
+template <typename T>
+constexpr int kPer = 256 / (CTile<T>::THREADS / CTile<T>::TP);
+
+template <typename T>
+__device__ __forceinline__ void fetch_tau(T (&v)[kPer<T>], const T* __restrict__ tau, int I, int J,
+                                          const CArgs& a) {
+  typedef CTile<T> C;
+  const int g = threadIdx.x / C::TP;
+  constexpr int G = C::THREADS / C::TP;
+  const int wl = g & 15;
+  if (I != J) {
+    const int64_t col = a.wl_off + (int64_t)J * 16 * a.nr;
+#pragma unroll
+    for (int it = 0; it < kPer<T>; ++it)
+      v[it] = tau[a.rbnr[I * 16 + (g >> 4) + it * (G >> 4)] + col];
+  } else {
+    const int64_t r = a.r0 + threadIdx.x % C::TP;
+#pragma unroll
+    for (int it = 0; it < kPer<T>; ++it) {
+      const int vl = (g >> 4) + it * (G >> 4);
+      const int lo = I * 16 + min(vl, wl), hi = I * 16 + max(vl, wl);
+      v[it] = tau[a.rbnr[lo] + (int64_t)hi * a.nr + r];
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_at(T (&v)[kPer<T>], const T* __restrict__ at, int K,
+                                         const CArgs& a) {
+  typedef CTile<T> C;
+  constexpr int G = C::THREADS / C::TP;
+  const T* base = at + a.a_off + (int64_t)K * 16 * a.nr;
+#pragma unroll
+  for (int it = 0; it < kPer<T>; ++it) v[it] = base[(int64_t)it * (G >> 4) * a.nr];
+}
+
+template <typename T>
+__device__ __forceinline__ void put_tile(T* s, const T (&v)[kPer<T>]) {
+  typedef CTile<T> C;
+  const int p = threadIdx.x % C::TP;
+  const int g = threadIdx.x / C::TP;
+  constexpr int G = C::THREADS / C::TP;
+#pragma unroll
+  for (int it = 0; it < kPer<T>; ++it)
+    s[C::at(((g >> 4) + it * (G >> 4)) * 16 + (g & 15), p)] = v[it];
+}
+
 template <typename T>
 __device__ __forceinline__ void load_at_full(T* s, const T* __restrict__ at, int K,
                                              const CArgs& a) {
@@ -142,23 +191,39 @@ __device__ __forceinline__ void load_at_full(T* s, const T* __restrict__ at, int
   }
 }
 
-// Walk of the upper triangle of (I, J) tiles, row by row.  The row tile I is a
-// compile-time constant (it selects acc[..][I]); the column tile J >= I is a
-// runtime loop, so the loads of each step are issued inside the loop; the
-// transposed contribution goes to acc[..][J] through a uniform branch chain.
-template <typename T, int NT, bool FULL, int I>
-__device__ __forceinline__ void row_walk(typename Mfma<T>::acc_t (&acc)[CTile<T>::PPW][NT],
+// Walk of the upper triangle of (I, J) tiles with runtime loops over the row
+// tile I and the column tile J >= I.  The accumulators acc[..][I] and
+// acc[..][J] are selected through uniform branch chains, so every register
+// index is a compile-time constant while no loads are hoisted out of the walk.
+template <int NT, typename T>
+__device__ __forceinline__ void mfma_into(typename Mfma<T>::acc_t (&acc)[NT], int tile,
+                                          const T (&x)[4], const T (&y)[4]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    if (tile == t) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[t] = Mfma<T>::run(x[k], y[k], acc[t]);
+    }
+}
+
+template <typename T, int NT, bool FULL>
+__device__ __forceinline__ void tri_walk(typename Mfma<T>::acc_t (&acc)[CTile<T>::PPW][NT],
                                          T* s_tau, T* s_a, const T* __restrict__ at,
                                          const T* __restrict__ tau, const CArgs& a) {
   typedef CTile<T> C;
-  if constexpr (I < NT) {
-    const int lx = a.lane & 15, ly = a.lane >> 4;
+  const int lx = a.lane & 15, ly = a.lane >> 4;
+  T pt[kPer<T>], pa[kPer<T>];  // prefetched tiles of the next step (full tiles only)
+#pragma unroll 1
+  for (int I = 0; I < NT; ++I) {
     // a[I] in LDS; its B' operands (v = 4k + ly, b = lx) kept in registers
     __syncthreads();
-    if constexpr (FULL)
-      load_at_full(s_a, at, I, a);
-    else
+    if constexpr (FULL) {
+      fetch_at(pa, at, I, a);
+      fetch_tau(pt, tau, I, I, a);
+      put_tile(s_a, pa);
+    } else {
       load_at(s_a, at, I, a.b0, a.nb, a.nocc, a.nr, a.r0);
+    }
     __syncthreads();
     T bI[C::PPW][4];
 #pragma unroll
@@ -170,38 +235,39 @@ __device__ __forceinline__ void row_walk(typename Mfma<T>::acc_t (&acc)[CTile<T>
     for (int J = I; J < NT; ++J) {
       __syncthreads();
       if constexpr (FULL) {
-        load_tau_full(s_tau, tau, I, J, a);
-        if (J != I) load_at_full(s_a, at, J, a);
+        put_tile(s_tau, pt);
+        if (J != I) put_tile(s_a, pa);
       } else {
         load_tau(s_tau, tau, I, J, a.nocc, a.nr, a.r0);
         if (J != I) load_at(s_a, at, J, a.b0, a.nb, a.nocc, a.nr, a.r0);
       }
       __syncthreads();
+      if constexpr (FULL) {
+        // the next step's loads are in flight while this step's MFMAs run
+        if (J + 1 < NT) {
+          fetch_tau(pt, tau, I, J + 1, a);
+          fetch_at(pa, at, J + 1, a);
+        }
+      }
 #pragma unroll
       for (int pp = 0; pp < C::PPW; ++pp) {
         const int p = a.wave * C::PPW + pp;
         // R[I] += tau[I][J] a[J]:  A[v][v'] = tau[v = lx][v' = 4k + ly], B = a[J][v' = 4k + ly][b = lx]
+        T x[4], y[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const T x = s_tau[C::at(lx * 16 + 4 * k + ly, p)];
-          const T y = s_a[C::at((4 * k + ly) * 16 + lx, p)];
-          acc[pp][I] = Mfma<T>::run(x, y, acc[pp][I]);
+          x[k] = s_tau[C::at(lx * 16 + 4 * k + ly, p)];
+          y[k] = s_a[C::at((4 * k + ly) * 16 + lx, p)];
         }
+        mfma_into<NT, T>(acc[pp], I, x, y);
         if (J != I) {
           // R[J] += tau[I][J]^T a[I]:  A'[v'][v] = tau[v = 4k + ly][v' = lx], B' = bI
-          T x2[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) x2[k] = s_tau[C::at((4 * k + ly) * 16 + lx, p)];
-#pragma unroll
-          for (int jj = I + 1; jj < NT; ++jj)
-            if (J == jj) {
-#pragma unroll
-              for (int k = 0; k < 4; ++k) acc[pp][jj] = Mfma<T>::run(x2[k], bI[pp][k], acc[pp][jj]);
-            }
+          for (int k = 0; k < 4; ++k) x[k] = s_tau[C::at((4 * k + ly) * 16 + lx, p)];
+          mfma_into<NT, T>(acc[pp], J, x, bI[pp]);
         }
       }
     }
-    row_walk<T, NT, FULL, I + 1>(acc, s_tau, s_a, at, tau, a);
   }
 }
 
@@ -286,7 +352,7 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
   for (int pp = 0; pp < C::PPW; ++pp)
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[pp][i] = acc_t{0, 0, 0, 0};
-  if (k1d) row_walk<T, NT, FULL, 0>(acc, s_tau, s_a, at, tau, a);
+  if (k1d) tri_walk<T, NT, FULL>(acc, s_tau, s_a, at, tau, a);
   const int64_t r = a.r0 + threadIdx.x % C::TP;
   const T fx = (r < nr && k1e) ? fxc[r] : T(0);
   write_rows<T, NT, 0>(acc, s_tau, phi, vh, drho, fx, ck, alpha, k1e, R, a);

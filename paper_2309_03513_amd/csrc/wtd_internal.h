@@ -63,10 +63,12 @@ constexpr int kStickTile = 16;
 template <typename T>
 void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
                               int per_trial, cplx<T>* wst, hipStream_t s);
+// With drho and a partial buffer part [ngroup][nb][nr], the orbital loop of each
+// trial is split over ngroup workgroups and the partial densities are summed.
 template <typename T>
 void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
                               int nfield_per_trial, T scale, T* out, const T* phi,
-                              T* drho, hipStream_t s);
+                              T* drho, hipStream_t s, T* part = nullptr, int ngroup = 1);
 template <typename T>
 void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads, int npack,
                              int limit, cplx<T>* dst, hipStream_t s);

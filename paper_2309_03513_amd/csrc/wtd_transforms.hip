@@ -14,6 +14,8 @@
 // and a plane pass (2D FFT over (i1, i2) at fixed i0, staged in LDS).  Two real
 // fields travel as the real and imaginary parts of one complex field (the
 // Gamma-point packing).  Stick data layout: [pack][i0 or k0][stick].
+#include <algorithm>
+
 #include "wtd_fft_ct.h"
 #include "wtd_internal.h"
 
@@ -144,7 +146,8 @@ __global__ void __launch_bounds__(kPlaneThreads)
 k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int n0, int n1,
                     int n2, int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
                     const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, T scale,
-                    T* __restrict__ out, const T* __restrict__ phi, T* __restrict__ drho) {
+                    T* __restrict__ out, const T* __restrict__ phi, T* __restrict__ drho,
+                    int ngroup, int nbtot) {
   extern __shared__ unsigned char smem_raw[];
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -152,12 +155,16 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   cplx<T>* twl = reinterpret_cast<cplx<T>*>(acc + (drho ? plane : 0));
   stage_twiddles<SN>(twl, tw1);
   const int i0 = blockIdx.x;
-  const int b = blockIdx.y;
+  // blockIdx.y = b * ngroup + group: the packs of trial b are split into
+  // ngroup contiguous groups; each group writes its own partial drho
+  const int b = blockIdx.y / ngroup, grp = blockIdx.y - b * ngroup;
+  const int per = (npt + ngroup - 1) / ngroup;
+  const int j0 = grp * per, j1 = min(npt, j0 + per);
   const int64_t nr = (int64_t)n0 * plane;
   const int64_t poff = (int64_t)i0 * plane;
   if (drho)
     for (int i = threadIdx.x; i < plane; i += blockDim.x) acc[i] = T(0);
-  for (int j = 0; j < npt; ++j) {
+  for (int j = j0; j < j1; ++j) {
     const int pack = b * npt + j;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
     __syncthreads();
@@ -183,9 +190,20 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
     __syncthreads();
   }
   if (drho) {
-    T* d = drho + (int64_t)b * nr + poff;
+    T* d = drho + ((int64_t)grp * nbtot + b) * nr + poff;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) d[i] = acc[i];
   }
+}
+
+// drho[b] = sum over groups of the partial densities (fixed order)
+template <typename T>
+__global__ void k_sum_groups(const T* __restrict__ part, int ngroup, int64_t n,
+                             T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = T(0);
+  for (int gr = 0; gr < ngroup; ++gr) s += part[(int64_t)gr * n + i];
+  out[i] = s;
 }
 
 // ---------------------------------------------------------------- pair products -> density sticks
@@ -586,14 +604,23 @@ void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int 
 template <typename T>
 void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int per_trial,
                               int nfield_per_trial, T scale, T* out, const T* phi, T* drho,
-                              hipStream_t s) {
+                              hipStream_t s, T* part, int ngroup) {
   (void)nfield_per_trial;
   const int npt = (per_trial + 1) / 2;
-  dim3 grid(g.n0, nb);
+  if (!drho || !part) ngroup = 1;
+  ngroup = std::max(1, std::min(ngroup, npt));
+  dim3 grid(g.n0, nb * ngroup);
   const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
+  T* dtarget = (ngroup > 1) ? part : drho;
   WTD_PLANE_LAUNCH(k_wsticks_to_fields, T, grid, lds, s, wst, npt, per_trial, g.n0, g.n1, g.n2,
                    g.nw, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
-                   static_cast<const cplx<T>*>(g.tw2), scale, out, phi, drho);
+                   static_cast<const cplx<T>*>(g.tw2), scale, out, phi, dtarget, ngroup, nb);
+  if (ngroup > 1) {
+    const int64_t n = (int64_t)nb * g.nr;
+    hipLaunchKernelGGL(k_sum_groups<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                       ngroup, n, drho);
+    WTD_HIP(hipGetLastError());
+  }
 }
 
 template <typename T>
@@ -700,7 +727,7 @@ void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_fl
   template void launch_sphere_to_wsticks<T>(const Geometry&, const T*, int, int, int, int,     \
                                             cplx<T>*, hipStream_t);                            \
   template void launch_wsticks_to_fields<T>(const Geometry&, const cplx<T>*, int, int, int, T, \
-                                            T*, const T*, T*, hipStream_t);                    \
+                                            T*, const T*, T*, hipStream_t, T*, int);           \
   template void launch_pairs_to_dsticks<T>(const Geometry&, const T*, const int4*, int, int,   \
                                            cplx<T>*, hipStream_t);                             \
   template void launch_dstick_poisson<T>(const Geometry&, cplx<T>*, int, hipStream_t);         \
