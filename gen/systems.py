@@ -9,8 +9,8 @@ not available, so every workload is synthetic.  The recipe:
   (|G|^2, m0, m1, m2) so that m = 0 comes first.
 * Orbitals: for each orbital (occupied first, then conduction) draw
   x ~ N(0,1) of shape (npw, 2), c(m) = (x0 + i x1) exp(-|G_m|^2/4), c(0) = x0;
-  then modified Gram-Schmidt, twice, in index order, with the Gamma inner
-  product <f|g> = sum_m w_m Re(conj(f_m) g_m), w_0 = 1, w_m = 2.
+  then Gram-Schmidt in index order, twice (as Cholesky QR), with the Gamma
+  inner product <f|g> = sum_m w_m Re(conj(f_m) g_m), w_0 = 1, w_m = 2.
 * Eigenvalues (Hartree): eps_v = -0.5 (Nocc - v)/Nocc for v = 1..Nocc (HOMO at
   0), eps_c = gap + 0.7 (c - 1)/Nc for c = 1..Nc.  The two slopes differ so the
   lowest transition energies are not exactly degenerate.
@@ -33,6 +33,7 @@ import dataclasses
 import math
 
 import numpy as np
+import scipy.linalg
 
 
 @dataclasses.dataclass(frozen=True)
@@ -158,13 +159,18 @@ def _decaying(rng, g2):
     return c
 
 
-def _mgs(c):
-    c = c.copy()
+def _gram_schmidt(c):
+    """Gram-Schmidt in index order under the Gamma inner product, done twice.
+
+    Each pass is a Cholesky QR: with the Gram matrix G = L L^T, the rows of
+    L^-1 c are the Gram-Schmidt vectors of c in index order (row i combines
+    rows 0..i with a positive weight on row i), the same set modified
+    Gram-Schmidt produces, up to rounding."""
+    sw = np.sqrt(_weights(c.shape[1]))
     for _ in range(2):
-        for i in range(c.shape[0]):
-            for j in range(i):
-                c[i] -= gamma_dot(c[j], c[i]) * c[j]
-            c[i] /= math.sqrt(gamma_dot(c[i], c[i]))
+        x = np.concatenate([c.real * sw, c.imag * sw], axis=1)
+        lo = np.linalg.cholesky(x @ x.T)
+        c = scipy.linalg.solve_triangular(lo, c, lower=True)
     c[:, 0] = c[:, 0].real
     return c
 
@@ -200,7 +206,7 @@ def make_system(cfg: Config, **overrides) -> System:
     if norb > 2 * mill.shape[0] - 1:
         raise ValueError("more orbitals than real plane-wave degrees of freedom")
     c = np.stack([_decaying(rng, g2) for _ in range(norb)])
-    c = _mgs(c)
+    c = _gram_schmidt(c)
     fxc = _fxc_field(rng, cfg, n)
     v = np.arange(1, cfg.nocc + 1, dtype=np.float64)
     eps_occ = -0.5 * (cfg.nocc - v) / cfg.nocc

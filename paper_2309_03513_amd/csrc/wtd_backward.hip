@@ -28,15 +28,6 @@ struct PTile {
   }
 };
 
-__device__ __forceinline__ int64_t pair_index(int v, int w, int nocc) {
-  if (v > w) {
-    const int t = v;
-    v = w;
-    w = t;
-  }
-  return (int64_t)v * nocc - (int64_t)v * (v - 1) / 2 + (w - v);
-}
-
 // X[b][K*16 + w] tile at q = 16 b_loc + w_loc (fields [b][nocc][nr])
 template <typename T>
 __device__ __forceinline__ void load_bw(T* s, const T* __restrict__ X, int K, int nb, int nocc,
@@ -57,11 +48,15 @@ __device__ __forceinline__ void load_bw(T* s, const T* __restrict__ X, int K, in
   }
 }
 
-// P[pair(w, v')] = sum_b (X[b][w] Y[b][v'] + Y[b][w] X[b][v']) for w <= v', nb <= 16
+// P[pair(w, v')] = sum_b (X[b][w] Y[b][v'] + Y[b][w] X[b][v']) for w in rows
+// [A0, A0 + nA) and v' in [B0, B0 + nB) (diag: A0 == B0 and w <= v'), nb <= 16.
+// Pair (w, v') is stored at local index i nA - i (i + 1) / 2 + j on the
+// diagonal (i = w - A0 <= j = v' - B0) and i nB + j off it.
 template <typename T>
 __global__ void __launch_bounds__(512)
 k_pair_density(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ X,
-               const T* __restrict__ Y, T* __restrict__ P) {
+               const T* __restrict__ Y, int A0, int nA, int B0, int nB, int diag,
+               T* __restrict__ P) {
   typedef PTile<T> C;
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T sXI[C::NE], sYI[C::NE], sXJ[C::NE], sYJ[C::NE];
@@ -71,20 +66,22 @@ k_pair_density(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ X,
   const int64_t r0 = (int64_t)tile * C::TP;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 15, ly = lane >> 4;
-  const int nt = (nocc + 15) / 16;
-  for (int I = 0; I < nt; ++I) {
+  const int ntA = (nA + 15) / 16, ntB = (nB + 15) / 16;
+  const int tA = A0 / 16, tB = B0 / 16;
+  for (int I = 0; I < ntA; ++I) {
     __syncthreads();
-    load_bw(sXI, X, I, nb, nocc, nr, r0);
-    load_bw(sYI, Y, I, nb, nocc, nr, r0);
-    for (int J = I; J < nt; ++J) {
+    load_bw(sXI, X, tA + I, nb, nocc, nr, r0);
+    load_bw(sYI, Y, tA + I, nb, nocc, nr, r0);
+    for (int J = diag ? I : 0; J < ntB; ++J) {
+      const bool same = diag && J == I;
       __syncthreads();
-      if (J != I) {
-        load_bw(sXJ, X, J, nb, nocc, nr, r0);
-        load_bw(sYJ, Y, J, nb, nocc, nr, r0);
+      if (!same) {
+        load_bw(sXJ, X, tB + J, nb, nocc, nr, r0);
+        load_bw(sYJ, Y, tB + J, nb, nocc, nr, r0);
       }
       __syncthreads();
-      const T* xj = (J != I) ? sXJ : sXI;
-      const T* yj = (J != I) ? sYJ : sYI;
+      const T* xj = same ? sXI : sXJ;
+      const T* yj = same ? sYI : sYJ;
       acc_t acc[C::PPW];
 #pragma unroll
       for (int pp = 0; pp < C::PPW; ++pp) {
@@ -114,9 +111,11 @@ k_pair_density(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ X,
 #pragma unroll
         for (int it = 0; it < 256 / G; ++it) {
           const int c = g + it * G;
-          const int w = I * 16 + (c >> 4), v = J * 16 + (c & 15);
-          if (w >= nocc || v >= nocc || w > v) continue;
-          P[pair_index(w, v, nocc) * nr + r] = sXJ[C::at(c, p)];
+          const int i = I * 16 + (c >> 4), j = J * 16 + (c & 15);
+          if (i >= nA || j >= nB || (diag && i > j)) continue;
+          const int64_t idx = diag ? (int64_t)i * nA - (int64_t)i * (i + 1) / 2 + j
+                                   : (int64_t)i * nB + j;
+          P[idx * nr + r] = sXJ[C::at(c, p)];
         }
       }
     }
@@ -164,16 +163,19 @@ __global__ void k_gamma_weights(T* __restrict__ x, int64_t nf, int npw, int mode
 }  // namespace
 
 template <typename T>
-void launch_pair_density(const Geometry& g, int nb, int nocc, const T* X, const T* Y, T* P,
-                         hipStream_t s) {
+void launch_pair_density(const Geometry& g, int nb, int nocc, const T* X, const T* Y, int A0,
+                         int nA, int B0, int nB, bool diag, T* P, hipStream_t s) {
   WTD_REQUIRE(nb <= 16, WTD_ERR_SHAPE, "pair densities support at most 16 trials per call");
+  WTD_REQUIRE(A0 % 16 == 0 && B0 % 16 == 0 && A0 + nA <= nocc && B0 + nB <= nocc &&
+                  (!diag || (A0 == B0 && nA == nB)),
+              WTD_ERR_SHAPE, "pair-density row blocks out of range");
   typedef PTile<T> C;
   const int64_t ntile64 = (g.nr + C::TP - 1) / C::TP;
   WTD_REQUIRE(ntile64 < (1ll << 30), WTD_ERR_SHAPE, "pair-density grid too large");
   const int ntile = (int)ntile64;
   const int per = (ntile + 7) / 8;
   hipLaunchKernelGGL(k_pair_density<T>, dim3(8 * per), dim3(C::THREADS), 0, s, nb, nocc, g.nr,
-                     ntile, X, Y, P);
+                     ntile, X, Y, A0, nA, B0, nB, diag ? 1 : 0, P);
   WTD_HIP(hipGetLastError());
 }
 
@@ -197,8 +199,8 @@ void launch_weights(T* x, int64_t nf, int npw, int mode, hipStream_t s) {
 }
 
 #define WTD_BWD_INST(T)                                                                        \
-  template void launch_pair_density<T>(const Geometry&, int, int, const T*, const T*, T*,      \
-                                       hipStream_t);                                           \
+  template void launch_pair_density<T>(const Geometry&, int, int, const T*, const T*, int, int, \
+                                       int, int, bool, T*, hipStream_t);                       \
   template void launch_gamma_k1e<T>(const Geometry&, int, int, T, const T*, const T*, const T*, \
                                     const T*, const T*, const T*, const T*, T*, hipStream_t);  \
   template void launch_weights<T>(T*, int64_t, int, int, hipStream_t);

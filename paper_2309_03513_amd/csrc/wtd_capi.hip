@@ -102,6 +102,14 @@ struct wtd_ctx {
   void* gbuf = nullptr;      // [max_nb][nocc][2 npw]
   int4* pquads = nullptr;    // packs of stored pair fields (2p, 2p+1)
   int* pidx = nullptr;       // [nocc][nocc]
+  // Row-blocked exchange (large Nocc): the pair triangle is split into blocks of
+  // row_block occupied rows; tau then holds the pairs of one block pair only.
+  int row_block = 0;         // 0: all pairs at once
+  struct BlockPair {
+    int A0, nA, B0, nB, diag;
+    int q0, npairs, npack;   // packs quads[q0 .. q0 + npack)
+  };
+  std::vector<BlockPair> bpairs;
   wtd::Profiler prof;
 };
 
@@ -414,19 +422,56 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   // pairs v <= v' (row-major), packed two per complex transform
   c->npairs = nocc * (nocc + 1) / 2;
   c->npack_pairs = (c->npairs + 1) / 2;
+  // Above 128 occupied orbitals the pair triangle is processed in blocks of 64
+  // rows (WTD_ROW_BLOCK = 16, 32, 48 or 64 selects blocking for any Nocc).
+  c->row_block = nocc > 128 ? 64 : 0;
+  if (const char* e = std::getenv("WTD_ROW_BLOCK")) {
+    const int rb = std::atoi(e);
+    WTD_REQUIRE(rb >= 0 && rb <= 64 && rb % 16 == 0, WTD_ERR_ARG,
+                "WTD_ROW_BLOCK must be 0, 16, 32, 48 or 64");
+    if (rb > 0) c->row_block = rb;
+  }
   {
     std::vector<int2> pr;
-    std::vector<int> pidx((size_t)nocc * nocc);
-    for (int v = 0; v < nocc; ++v)
-      for (int w = v; w < nocc; ++w) {
-        pidx[(size_t)v * nocc + w] = pidx[(size_t)w * nocc + v] = (int)pr.size();
-        pr.push_back(int2{v, w});
+    std::vector<int> pidx;
+    std::vector<int4> q;
+    auto pack = [&](size_t first) {
+      for (size_t p = first; p < pr.size(); p += 2) {
+        const int2 a = pr[p];
+        const int2 b = (p + 1 < pr.size()) ? pr[p + 1] : int2{-1, -1};
+        q.push_back(int4{a.x, a.y, b.x, b.y});
       }
-    std::vector<int4> q(c->npack_pairs);
-    for (int p = 0; p < c->npack_pairs; ++p) {
-      const int2 a = pr[2 * p];
-      const int2 b = (2 * p + 1 < c->npairs) ? pr[2 * p + 1] : int2{-1, -1};
-      q[p] = int4{a.x, a.y, b.x, b.y};
+    };
+    if (c->row_block == 0) {
+      pidx.resize((size_t)nocc * nocc);
+      for (int v = 0; v < nocc; ++v)
+        for (int w = v; w < nocc; ++w) {
+          pidx[(size_t)v * nocc + w] = pidx[(size_t)w * nocc + v] = (int)pr.size();
+          pr.push_back(int2{v, w});
+        }
+      pack(0);
+    } else {
+      // block pairs (A, B), A <= B; the diagonal block stores its upper
+      // triangle row-major, an off-diagonal block its full rectangle
+      const int rb = c->row_block;
+      for (int A0 = 0; A0 < nocc; A0 += rb)
+        for (int B0 = A0; B0 < nocc; B0 += rb) {
+          wtd_ctx::BlockPair bp;
+          bp.A0 = A0;
+          bp.nA = std::min(rb, nocc - A0);
+          bp.B0 = B0;
+          bp.nB = std::min(rb, nocc - B0);
+          bp.diag = A0 == B0;
+          const size_t first = pr.size();
+          for (int i = 0; i < bp.nA; ++i)
+            for (int j = bp.diag ? i : 0; j < bp.nB; ++j) pr.push_back(int2{A0 + i, B0 + j});
+          bp.q0 = (int)q.size();
+          bp.npairs = (int)(pr.size() - first);
+          pack(first);
+          bp.npack = (int)q.size() - bp.q0;
+          c->bpairs.push_back(bp);
+        }
+      pidx.resize(1);
     }
     c->quads = (int4*)dalloc(c, q.size() * sizeof(int4));
     h2d(c, c->quads, q.data(), q.size() * sizeof(int4));
@@ -449,13 +494,18 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->drho = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->drho_part = dalloc(c, (size_t)kDrhoGroups * mnb * nr * sizeof(T));
-  if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D)) c->tau = dalloc(c, (size_t)c->npairs * nr * sizeof(T));
+  const size_t tau_fields =
+      c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs) : c->npairs;
+  if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D))
+    c->tau = dalloc(c, tau_fields * nr * sizeof(T));
   c->wst = dalloc(c, nwp * c->g.n0 * c->g.nw * sizeof(cplx<T>));
   // packed pairs per Poisson batch; the density-stick intermediate of one batch
   // is batch * n0 * n_d complex values (WTD_PAIR_CHUNK overrides the default)
   int chunk = 512;
   if (const char* e = std::getenv("WTD_PAIR_CHUNK")) chunk = std::max(1, std::atoi(e));
   c->pair_chunk = std::max(1, std::min(c->npack_pairs, chunk));
+  if (c->row_block)
+    c->pair_chunk = std::min(c->pair_chunk, (int)((tau_fields + 1) / 2));
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
   c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nd * sizeof(cplx<T>));
   c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
@@ -512,8 +562,33 @@ void apply_core(wtd_ctx* c, int nb) {
     launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, nh, s);
     launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, nh, nb, (T*)c->vh, s);
   }
+  if (c->row_block) {
+    // 5'-6'. R = response term, then the exchange sum block pair by block pair
+    prof_next(c, 6);
+    launch_response_rows<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->vh, (const T*)c->drho,
+                            (const T*)c->fxc, (T)c->ck, k1e, (T*)c->R, s);
+    if (k1d) {
+      for (const auto& bp : c->bpairs) {
+        for (int p0 = 0; p0 < bp.npack; p0 += c->pair_chunk) {
+          const int np = std::min(c->pair_chunk, bp.npack - p0);
+          const int nf = std::min(2 * np, bp.npairs - 2 * p0);
+          prof_next(c, 3);
+          launch_pairs_to_dsticks<T>(g, (const T*)c->phi, c->quads + bp.q0 + p0, np, c->nocc,
+                                     (cplx<T>*)c->dst, s);
+          prof_next(c, 4);
+          launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
+          prof_next(c, 5);
+          launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
+                                      (T*)c->tau + (int64_t)2 * p0 * g.nr, s);
+        }
+        prof_next(c, 6);
+        launch_contract_block<T>(g, nb, nocc, (const T*)c->at, (const T*)c->tau, bp.A0, bp.nA,
+                                 bp.B0, bp.nB, bp.diag != 0, (T)c->alpha, (T*)c->R, s);
+      }
+    }
+  }
   // 5. pair potentials, in chunks of packed pairs
-  if (k1d) {
+  if (k1d && !c->row_block) {
     for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
       const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
       const int nf = std::min(2 * np, c->npairs - 2 * p0);
@@ -529,7 +604,8 @@ void apply_core(wtd_ctx* c, int nb) {
   }
   // 6. R
   prof_next(c, 6);
-  if (!launch_contract_mfma<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau,
+  if (c->row_block) {
+  } else if (!launch_contract_mfma<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau,
                                (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
                                (T)c->alpha, k1e, k1d, (T*)c->R, s))
     launch_contract<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau, c->pidx,
@@ -656,8 +732,29 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
   launch_wsticks_to_fields<T>(G, (const cplx<T>*)c->wst, nb, nocc, nocc, iso, (T*)c->gt,
                               (const T*)c->phi, k1e ? (T*)c->drhog : nullptr, s);
   // exchange part: P_wv' = M_wv' + M_v'w -> v_c * P -> gamma = -alpha sum_v' phi_v' (v_c * P)
-  if (k1d) {
-    launch_pair_density<T>(G, nb, nocc, (const T*)c->gt, (const T*)c->at, (T*)c->tau, s);
+  if (k1d && c->row_block) {
+    // gamma = -alpha sum_v' phi_v' v_c * P_wv', block pair by block pair
+    launch_response_rows<T>(G, 1, nocc, (const T*)c->phi, nullptr, nullptr, nullptr, (T)0, false,
+                            (T*)c->gamma, s);
+    for (const auto& bp : c->bpairs) {
+      launch_pair_density<T>(G, nb, nocc, (const T*)c->gt, (const T*)c->at, bp.A0, bp.nA, bp.B0,
+                             bp.nB, bp.diag != 0, (T*)c->tau, s);
+      const int npk = (bp.npairs + 1) / 2;
+      for (int p0 = 0; p0 < npk; p0 += c->pair_chunk) {
+        const int np = std::min(c->pair_chunk, npk - p0);
+        const int nf = std::min(2 * np, bp.npairs - 2 * p0);
+        launch_pairs_to_dsticks<T>(G, (const T*)c->tau + (int64_t)2 * p0 * G.nr, c->pquads, np,
+                                   nf, (cplx<T>*)c->dst, s);
+        launch_dstick_poisson<T>(G, (cplx<T>*)c->dst, np, s);
+        launch_dsticks_to_fields<T>(G, (const cplx<T>*)c->dst, np, nf,
+                                    (T*)c->tau + (int64_t)2 * p0 * G.nr, s);
+      }
+      launch_contract_block<T>(G, 1, nocc, (const T*)c->phi, (const T*)c->tau, bp.A0, bp.nA,
+                               bp.B0, bp.nB, bp.diag != 0, (T)c->alpha, (T*)c->gamma, s);
+    }
+  } else if (k1d) {
+    launch_pair_density<T>(G, nb, nocc, (const T*)c->gt, (const T*)c->at, 0, nocc, 0, nocc, true,
+                           (T*)c->tau, s);
     for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
       const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
       const int nf = std::min(2 * np, c->npairs - 2 * p0);

@@ -358,6 +358,158 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
   write_rows<T, NT, 0>(acc, s_tau, phi, vh, drho, fx, ck, alpha, k1e, R, a);
 }
 
+// ---------------------------------------------------------------------------
+// Block form for large Nocc: the pair triangle is processed in blocks of rows
+// (A, B), A <= B, of at most 4 row tiles each.  tau holds the block's pairs:
+// a rectangle (v in A, w in B) stored row-major, or, for A == B, the upper
+// triangle (w >= v) stored row-major.  The kernel adds
+//   R[A] -= alpha tau[A][B] a[B]   and, for A != B,   R[B] -= alpha tau[A][B]^T a[A]
+// to R (read-modify-write).  Accumulator slots 0..3 hold R[A] tiles, 4..7 R[B].
+struct BArgs {
+  int A0, nA, B0, nB, diag;
+};
+
+template <typename T>
+__device__ __forceinline__ int64_t block_pair(const BArgs& bk, int i, int j) {
+  // i, j local row / column indices inside the block
+  if (bk.diag) {
+    if (i > j) {
+      const int t = i;
+      i = j;
+      j = t;
+    }
+    return (int64_t)i * bk.nA - (int64_t)i * (i + 1) / 2 + j;
+  }
+  return (int64_t)i * bk.nB + j;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tau_block(T* s, const T* __restrict__ tau, int I, int J,
+                                               const BArgs& bk, int64_t nr, int64_t r0) {
+  typedef CTile<T> C;
+  const int p = threadIdx.x % C::TP;
+  const int g = threadIdx.x / C::TP;
+  constexpr int G = C::THREADS / C::TP;
+  const int64_t r = r0 + p;
+  const bool rin = r < nr;
+#pragma unroll
+  for (int it = 0; it < 256 / G; ++it) {
+    const int c = g + it * G;
+    const int i = I * 16 + (c >> 4), j = J * 16 + (c & 15);
+    T val = T(0);
+    if (rin && i < bk.nA && j < (bk.diag ? bk.nA : bk.nB))
+      val = tau[block_pair<T>(bk, i, j) * nr + r];
+    s[C::at(c, p)] = val;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CTile<T>::THREADS)
+k_contract_block(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ at,
+                 const T* __restrict__ tau, BArgs bk, T alpha, T* __restrict__ R) {
+  typedef CTile<T> C;
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T s_tau[C::NE];
+  __shared__ T s_a[C::NE];
+  const int per = (ntile + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntile) return;
+  const int b0 = blockIdx.y * 16;
+  const int64_t r0 = (int64_t)tile * C::TP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 15, ly = lane >> 4;
+  const int ntA = (bk.nA + 15) / 16, ntB = bk.diag ? ntA : (bk.nB + 15) / 16;
+  acc_t acc[C::PPW][8];
+#pragma unroll
+  for (int pp = 0; pp < C::PPW; ++pp)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[pp][i] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+  for (int I = 0; I < ntA; ++I) {
+    // a at the rows of tile I of block A (B' operands of the transposed term)
+    __syncthreads();
+    load_at(s_a, at, bk.A0 / 16 + I, b0, nb, nocc, nr, r0);
+    __syncthreads();
+    T bI[C::PPW][4];
+#pragma unroll
+    for (int pp = 0; pp < C::PPW; ++pp)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        bI[pp][k] = s_a[C::at((4 * k + ly) * 16 + lx, wave * C::PPW + pp)];
+#pragma unroll 1
+    for (int J = bk.diag ? I : 0; J < ntB; ++J) {
+      const bool dtile = bk.diag && J == I;
+      __syncthreads();
+      load_tau_block(s_tau, tau, I, J, bk, nr, r0);
+      if (!dtile) load_at(s_a, at, (bk.diag ? bk.A0 : bk.B0) / 16 + J, b0, nb, nocc, nr, r0);
+      __syncthreads();
+      const int slotI = I;
+      const int slotJ = bk.diag ? J : 4 + J;
+#pragma unroll
+      for (int pp = 0; pp < C::PPW; ++pp) {
+        const int p = wave * C::PPW + pp;
+        T x[4], y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          x[k] = s_tau[C::at(lx * 16 + 4 * k + ly, p)];
+          y[k] = s_a[C::at((4 * k + ly) * 16 + lx, p)];
+        }
+        mfma_into<8, T>(acc[pp], slotI, x, y);
+        if (!dtile) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) x[k] = s_tau[C::at((4 * k + ly) * 16 + lx, p)];
+          mfma_into<8, T>(acc[pp], slotJ, x, bI[pp]);
+        }
+      }
+    }
+  }
+  // R += -alpha acc for the rows of A (slots 0..3) and, off the diagonal, of B (4..7)
+  const int p = threadIdx.x % C::TP;
+  const int g = threadIdx.x / C::TP;
+  constexpr int G = C::THREADS / C::TP;
+  const int64_t r = r0 + p;
+#pragma unroll
+  for (int slot = 0; slot < 8; ++slot) {
+    const bool isA = slot < 4;
+    const int tl = isA ? slot : slot - 4;
+    if (!isA && bk.diag) break;
+    const int base = isA ? bk.A0 : bk.B0;
+    const int nrows = isA ? bk.nA : bk.nB;
+    if (tl * 16 >= nrows) continue;
+    __syncthreads();
+#pragma unroll
+    for (int pp = 0; pp < C::PPW; ++pp)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        s_tau[C::at(Mfma<T>::row(lane, e) * 16 + lx, wave * C::PPW + pp)] = acc[pp][slot][e];
+    __syncthreads();
+    if (r < nr) {
+#pragma unroll
+      for (int it = 0; it < 256 / G; ++it) {
+        const int c = g + it * G;
+        const int vl = tl * 16 + (c >> 4), b = b0 + (c & 15);
+        if (vl >= nrows || b >= nb) continue;
+        T* o = R + ((int64_t)b * nocc + base + vl) * nr + r;
+        *o += -alpha * s_tau[C::at(c, p)];
+      }
+    }
+  }
+}
+
+// R[b][v] = c_K phi_v (v_H,b + f_xc drho_b), or 0 without the response term
+template <typename T>
+__global__ void k_response_rows(int nb, int nocc, int64_t nr, const T* __restrict__ phi,
+                                const T* __restrict__ vh, const T* __restrict__ drho,
+                                const T* __restrict__ fxc, T ck, int k1e, T* __restrict__ R) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int bv = blockIdx.y;
+  if (r >= nr) return;
+  const int b = bv / nocc, v = bv - b * nocc;
+  T val = T(0);
+  if (k1e) val = ck * phi[(int64_t)v * nr + r] * (vh[(int64_t)b * nr + r] + fxc[r] * drho[(int64_t)b * nr + r]);
+  R[(int64_t)bv * nr + r] = val;
+}
+
 }  // namespace
 
 template <typename T>
@@ -408,5 +560,47 @@ template bool launch_contract_mfma<double>(const Geometry&, int, int, const doub
                                            const double*, const double*, const double*,
                                            const double*, const double*, double, double, bool,
                                            bool, double*, hipStream_t);
+
+}  // namespace wtd
+
+namespace wtd {
+
+template <typename T>
+void launch_response_rows(const Geometry& g, int nb, int nocc, const T* phi, const T* vh,
+                          const T* drho, const T* fxc, T ck, bool k1e, T* R, hipStream_t s) {
+  dim3 grid((unsigned)((g.nr + 255) / 256), (unsigned)(nb * nocc));
+  hipLaunchKernelGGL(k_response_rows<T>, grid, dim3(256), 0, s, nb, nocc, g.nr, phi, vh, drho, fxc,
+                     ck, (int)k1e, R);
+  WTD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, const T* tau, int A0,
+                           int nA, int B0, int nB, bool diag, T alpha, T* R, hipStream_t s) {
+  WTD_REQUIRE(nA <= 64 && nB <= 64 && A0 % 16 == 0 && B0 % 16 == 0, WTD_ERR_SHAPE,
+              "row blocks of the exchange contraction must be <= 64 rows, 16-aligned");
+  typedef CTile<T> C;
+  const int64_t ntile64 = (g.nr + C::TP - 1) / C::TP;
+  WTD_REQUIRE(ntile64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
+  const int ntile = (int)ntile64;
+  const int per = (ntile + 7) / 8;
+  dim3 grid(8 * per, (nb + 15) / 16);
+  BArgs bk{A0, nA, B0, nB, diag ? 1 : 0};
+  hipLaunchKernelGGL(k_contract_block<T>, grid, dim3(C::THREADS), 0, s, nb, nocc, g.nr, ntile, at,
+                     tau, bk, alpha, R);
+  WTD_HIP(hipGetLastError());
+}
+
+template void launch_response_rows<float>(const Geometry&, int, int, const float*, const float*,
+                                          const float*, const float*, float, bool, float*,
+                                          hipStream_t);
+template void launch_response_rows<double>(const Geometry&, int, int, const double*,
+                                           const double*, const double*, const double*, double,
+                                           bool, double*, hipStream_t);
+template void launch_contract_block<float>(const Geometry&, int, int, const float*, const float*,
+                                           int, int, int, int, bool, float, float*, hipStream_t);
+template void launch_contract_block<double>(const Geometry&, int, int, const double*,
+                                            const double*, int, int, int, int, bool, double,
+                                            double*, hipStream_t);
 
 }  // namespace wtd

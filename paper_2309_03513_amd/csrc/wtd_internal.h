@@ -96,10 +96,22 @@ bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, con
                           const T* tau, const T* vh, const T* drho, const T* fxc, T ck, T alpha,
                           bool k1e, bool k1d, T* R, hipStream_t s);
 
-// Backward kernels (wtd_backward.hip).
+// Block form of the exchange contraction for large Nocc (wtd_contract.hip):
+// R = c_K phi (v_H + f_xc drho) first, then per row block pair (A, B)
+// R[A] -= alpha tau a[B] and R[B] -= alpha tau^T a[A] (tau of the block only).
 template <typename T>
-void launch_pair_density(const Geometry& g, int nb, int nocc, const T* X, const T* Y, T* P,
-                         hipStream_t s);
+void launch_response_rows(const Geometry& g, int nb, int nocc, const T* phi, const T* vh,
+                          const T* drho, const T* fxc, T ck, bool k1e, T* R, hipStream_t s);
+template <typename T>
+void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, const T* tau, int A0,
+                           int nA, int B0, int nB, bool diag, T alpha, T* R, hipStream_t s);
+
+// Backward kernels (wtd_backward.hip).
+// Pair densities of rows [A0, A0 + nA) x [B0, B0 + nB) (diag: the upper
+// triangle of one block), stored in the block layout of the pair pipeline.
+template <typename T>
+void launch_pair_density(const Geometry& g, int nb, int nocc, const T* X, const T* Y, int A0,
+                         int nA, int B0, int nB, bool diag, T* P, hipStream_t s);
 template <typename T>
 void launch_gamma_k1e(const Geometry& g, int nb, int nocc, T ck, const T* gt, const T* at,
                       const T* vh, const T* drho, const T* vhg, const T* drhog, const T* fxc,
