@@ -28,6 +28,35 @@ MEV = 3.674932e-5  # Hartree per meV
 METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at ΔE≤1 meV"
 
 
+# HBM bytes per launch of the dominant kernel measured with rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (scaled by a plain-copy calibration), valid only for the kernel
+# sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
+MEASURED_TRAFFIC = {
+    "contract": {
+        "bytes": 23722e6,
+        "sources": {
+            "paper_2309_03513_amd/csrc/wtd_contract.hip":
+                "fa31f360ec3b4b121a9eaea8eaf1f4b745db40a7e7306ca076efbe98c9a46ef2",
+            "paper_2309_03513_amd/csrc/wtd_mfma.h":
+                "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
+        },
+    },
+}
+
+
+def measured_traffic(stage):
+    """Counter-measured bytes per launch of `stage`, or None if its sources changed since."""
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(stage)
+    if rec is None:
+        return None
+    for rel, digest in rec["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return rec["bytes"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -102,11 +131,16 @@ def accuracy_fp32(s, nb, nroots):
 
 
 def cpu_baseline(s, nb, a_np, rows=(0, 1, 2)):
-    """Time the oracle on a bounded sample of the same block and extrapolate per row."""
+    """Time the oracle on a bounded sample of the same block and extrapolate per row.
+
+    A one-trial, one-row call first warms the FFT plans and the allocator; then
+    the same block is applied for output row 0 and for rows 0..2, and the block
+    time is the fixed part plus Nocc times the per-row part."""
     import oracle
     import oracle.planewave as pw
     cores = len(os.sched_getaffinity(0))
     pw._WORKERS = cores
+    oracle.apply_liouville(s, a_np[:1], rows=[rows[0]])
     t0 = time.perf_counter()
     oracle.apply_liouville(s, a_np, rows=[rows[0]])
     t1 = time.perf_counter()
@@ -181,7 +215,7 @@ def main():
     dom_ms = st[dom][0] / st[dom][1]
     achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "algorithmic_bytes_per_launch": ab[dom], "mean_launch_ms": dom_ms}
 
     acc = None if args.no_accuracy else accuracy_fp32(s, nb, cfg.nroots)

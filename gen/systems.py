@@ -78,6 +78,9 @@ CONFIGS = {
                  ncond=9, gap=0.2, nb=3, nroots=3, seed=12),
     "p3": Config("p3", *_cubic(13.5, 72), ecut_ry=40.0, nocc=36, ncond=20, gap=0.15,
                  nb=7, nroots=4, seed=13),
+    # more than 128 occupied orbitals (row-blocked exchange: blocks 64, 64, 16)
+    "p4": Config("p4", *_cubic(12.0, 36), ecut_ry=20.0, nocc=144, ncond=24, gap=0.15,
+                 nb=3, nroots=3, seed=14),
 }
 
 

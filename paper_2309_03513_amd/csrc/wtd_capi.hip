@@ -300,6 +300,9 @@ void build_geometry(wtd_ctx* c, const wtd_system* sys) {
     wk12.push_back(kv.first);
   }
   g.nw = (int)wk12.size();
+  // stick rows start on 128-byte boundaries, so the 16-stick tiles of the
+  // stick kernels never share a cache line
+  g.nws = (g.nw + 15) / 16 * 16;
   g.nwtile = (g.nw + kStickTile - 1) / kStickTile;
   std::vector<std::vector<int4>> tiles(g.nwtile);
   std::vector<int> pos(2 * (size_t)npw);
@@ -313,7 +316,7 @@ void build_geometry(wtd_ctx* c, const wtd_system* sys) {
       const int k1 = fold(sg * mill[3 * h + 1], n[1]), k2 = fold(sg * mill[3 * h + 2], n[2]);
       const int s = wkey[k1 * n[2] + k2];
       tiles[s / kStickTile].push_back(int4{h, sg, s % kStickTile, k0});
-      pos[2 * h + (sg > 0 ? 0 : 1)] = k0 * g.nw + s;
+      pos[2 * h + (sg > 0 ? 0 : 1)] = k0 * g.nws + s;
     }
   }
   std::vector<int> off(g.nwtile + 1, 0);
@@ -347,6 +350,7 @@ void build_geometry(wtd_ctx* c, const wtd_system* sys) {
     }
   std::vector<int> dk12(dkey.begin(), dkey.end());
   g.nd = (int)dk12.size();
+  g.nds = (g.nd + 15) / 16 * 16;
   int* d_dk = (int*)dalloc(c, dk12.size() * sizeof(int));
   upload(c, d_dk, dk12);
   g.dst_k12 = d_dk;
@@ -498,7 +502,7 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
       c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs) : c->npairs;
   if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D))
     c->tau = dalloc(c, tau_fields * nr * sizeof(T));
-  c->wst = dalloc(c, nwp * c->g.n0 * c->g.nw * sizeof(cplx<T>));
+  c->wst = dalloc(c, nwp * c->g.n0 * c->g.nws * sizeof(cplx<T>));
   // packed pairs per Poisson batch; the density-stick intermediate of one batch
   // is batch * n0 * n_d complex values (WTD_PAIR_CHUNK overrides the default)
   int chunk = 512;
@@ -507,7 +511,7 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   if (c->row_block)
     c->pair_chunk = std::min(c->pair_chunk, (int)((tau_fields + 1) / 2));
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
-  c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nd * sizeof(cplx<T>));
+  c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nds * sizeof(cplx<T>));
   c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
   c->rg = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
   c->S = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));

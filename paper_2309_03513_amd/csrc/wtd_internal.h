@@ -45,6 +45,7 @@ struct Geometry {
   const void* tw2;
   // wave sticks: columns along i0 of the wave-function sphere
   int nw;                 // number of wave sticks
+  int nws;                // stick row stride of wave-stick buffers (nw rounded up to 16)
   const int* wst_k12;     // [nw] k1*n2 + k2
   int nwtile;             // stick tiles for the sphere->stick scatter
   const int* wtile_off;   // [nwtile+1] CSR offsets into wtile_ent
@@ -52,6 +53,7 @@ struct Geometry {
   const int2* sph_pos;    // [npw] (stick*n0 + k0) of +m and of -m
   // density sticks: columns that pair products can occupy
   int nd;
+  int nds;                // stick row stride of density-stick buffers (nd rounded up to 16)
   const int* dst_k12;     // [nd]
   const void* dkern;      // [nd][n0] Coulomb kernel / N_r, working precision
 };

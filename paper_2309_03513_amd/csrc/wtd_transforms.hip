@@ -86,6 +86,15 @@ __device__ __forceinline__ void stick_fft(cplx<T>* buf, const FFTPlan& P0, const
     lds_fft<S, MB, true>(buf, P0, kStickTile, kStickTile, 1, tw0);
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by linear id.  xcd_item maps a
+// linear id to a work item so that each XCD walks a contiguous range of items:
+// items sharing inputs then meet in the same L2.  Returns -1 for the padding ids.
+__device__ __forceinline__ int xcd_item(int total) {
+  const int per = (total + 7) >> 3;
+  const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  return w < total ? w : -1;
+}
+
 // copy an N-entry twiddle table into LDS (callers synchronise before use)
 template <int SN, typename T>
 __device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) {
@@ -98,6 +107,7 @@ __device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) 
 template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
 k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw, int n0, int nw,
+                    int nws,
                     const int* __restrict__ off, const int4* __restrict__ ent, FFTPlan P0,
                     const cplx<T>* __restrict__ tw0, cplx<T>* __restrict__ wst) {
   extern __shared__ unsigned char smem_raw[];
@@ -130,11 +140,11 @@ k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw,
   }
   __syncthreads();
   stick_fft<+1, SN, MB>(buf, P0, tw0, twl);
-  cplx<T>* out = wst + (int64_t)pack * n0 * nw;
+  cplx<T>* out = wst + (int64_t)pack * n0 * nws;
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
-    if (s < nw) out[(int64_t)i0 * nw + s] = buf[i];
+    if (s < nw) out[(int64_t)i0 * nws + s] = buf[i];
   }
 }
 
@@ -144,7 +154,7 @@ k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw,
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int n0, int n1,
-                    int n2, int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                    int n2, int nw, int nws, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
                     const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, T scale,
                     T* __restrict__ out, const T* __restrict__ phi, T* __restrict__ drho,
                     int ngroup, int nbtot) {
@@ -153,11 +163,16 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   T* acc = reinterpret_cast<T*>(pl + plane);
   cplx<T>* twl = reinterpret_cast<cplx<T>*>(acc + (drho ? plane : 0));
+  // item = (i0, group, b), b fastest: the trials of one (plane, orbital group)
+  // read the same orbital planes and run back to back on one XCD.  The packs
+  // of trial b are split into ngroup contiguous groups; each group writes its
+  // own partial drho.
+  const int item = xcd_item(n0 * ngroup * nbtot);
+  if (item < 0) return;
   stage_twiddles<SN>(twl, tw1);
-  const int i0 = blockIdx.x;
-  // blockIdx.y = b * ngroup + group: the packs of trial b are split into
-  // ngroup contiguous groups; each group writes its own partial drho
-  const int b = blockIdx.y / ngroup, grp = blockIdx.y - b * ngroup;
+  const int i0 = item / (ngroup * nbtot);
+  const int rem = item - i0 * ngroup * nbtot;
+  const int grp = rem / nbtot, b = rem - grp * nbtot;
   const int per = (npt + ngroup - 1) / ngroup;
   const int j0 = grp * per, j1 = min(npt, j0 + per);
   const int64_t nr = (int64_t)n0 * plane;
@@ -168,7 +183,7 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
     const int pack = b * npt + j;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
     __syncthreads();
-    const cplx<T>* src = wst + ((int64_t)pack * n0 + i0) * nw;
+    const cplx<T>* src = wst + ((int64_t)pack * n0 + i0) * nws;
     for (int s = threadIdx.x; s < nw; s += blockDim.x) pl[k12[s]] = src[s];
     __syncthreads();
     plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
@@ -211,17 +226,23 @@ __global__ void k_sum_groups(const T* __restrict__ part, int ngroup, int64_t n,
 // c < 0 means no imaginary part.
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
-k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, int limit, int n0,
-                   int n1, int n2, int nd, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, int npack, int limit,
+                   int n0,
+                   int n1, int n2, int nd, int nds, const int* __restrict__ k12, FFTPlan P1,
+                   FFTPlan P2,
                    const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
                    cplx<T>* __restrict__ dst) {
   extern __shared__ unsigned char smem_raw[];
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* twl = pl + plane;
+  // item = (i0, pack), pack fastest: an XCD works through its planes one at a
+  // time, so the orbital planes of the current i0 stay in its L2
+  const int item = xcd_item(n0 * npack);
+  if (item < 0) return;
   stage_twiddles<SN>(twl, tw1);
-  const int i0 = blockIdx.x;
-  const int pack = blockIdx.y;
+  const int i0 = item / npack;
+  const int pack = item - i0 * npack;
   const int64_t nr = (int64_t)n0 * plane;
   const int64_t poff = (int64_t)i0 * plane;
   int4 q = quads[pack];
@@ -237,7 +258,7 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
   }
   __syncthreads();
   plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nd;
+  cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nds;
   for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
 }
 
@@ -246,20 +267,20 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
 // inverse FFT along i0; in place.
 template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
-k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict__ kern,
+k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, int nds, const T* __restrict__ kern,
                  FFTPlan P0, const cplx<T>* __restrict__ tw0) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tile = blockIdx.x;
   const int pack = blockIdx.y;
-  cplx<T>* base = dst + (int64_t)pack * n0 * nd;
+  cplx<T>* base = dst + (int64_t)pack * n0 * nds;
   const int tot = n0 * kStickTile;
   cplx<T>* twl = buf + tot;
   stage_twiddles<SN>(twl, tw0);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
-    buf[i] = (s < nd) ? base[(int64_t)i0 * nd + s] : cplx<T>{T(0), T(0)};
+    buf[i] = (s < nd) ? base[(int64_t)i0 * nds + s] : cplx<T>{T(0), T(0)};
   }
   __syncthreads();
   stick_fft<-1, SN, MB>(buf, P0, tw0, twl);
@@ -274,7 +295,7 @@ k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict_
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
-    if (s < nd) base[(int64_t)i0 * nd + s] = buf[i];
+    if (s < nd) base[(int64_t)i0 * nds + s] = buf[i];
   }
 }
 
@@ -282,6 +303,7 @@ k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, const T* __restrict_
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1, int n2, int nd,
+                    int nds,
                     const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
                     const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
                     T* __restrict__ out) {
@@ -295,7 +317,7 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
   const int64_t nr = (int64_t)n0 * plane;
   for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
   __syncthreads();
-  const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nd;
+  const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
   for (int s = threadIdx.x; s < nd; s += blockDim.x) pl[k12[s]] = src[s];
   __syncthreads();
   plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
@@ -313,7 +335,7 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int n0, int n1, int n2,
-                    int nw, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                    int nw, int nws, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
                     const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
                     cplx<T>* __restrict__ wst) {
   extern __shared__ unsigned char smem_raw[];
@@ -331,34 +353,34 @@ k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int n0
   for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {f1[i], f2 ? f2[i] : T(0)};
   __syncthreads();
   plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nw;
+  cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nws;
   for (int s = threadIdx.x; s < nw; s += blockDim.x) o[s] = pl[k12[s]];
 }
 
 // ---------------------------------------------------------------- wave sticks: forward along i0
 template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
-k_wsticks_forward(cplx<T>* __restrict__ wst, int n0, int nw, FFTPlan P0,
+k_wsticks_forward(cplx<T>* __restrict__ wst, int n0, int nw, int nws, FFTPlan P0,
                   const cplx<T>* __restrict__ tw0) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tile = blockIdx.x;
   const int pack = blockIdx.y;
-  cplx<T>* base = wst + (int64_t)pack * n0 * nw;
+  cplx<T>* base = wst + (int64_t)pack * n0 * nws;
   const int tot = n0 * kStickTile;
   cplx<T>* twl = buf + tot;
   stage_twiddles<SN>(twl, tw0);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int i0 = i / kStickTile, l = i - i0 * kStickTile;
     const int s = tile * kStickTile + l;
-    buf[i] = (s < nw) ? base[(int64_t)i0 * nw + s] : cplx<T>{T(0), T(0)};
+    buf[i] = (s < nw) ? base[(int64_t)i0 * nws + s] : cplx<T>{T(0), T(0)};
   }
   __syncthreads();
   stick_fft<-1, SN, MB>(buf, P0, tw0, twl);
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int k0 = i / kStickTile, l = i - k0 * kStickTile;
     const int s = tile * kStickTile + l;
-    if (s < nw) base[(int64_t)k0 * nw + s] = buf[i];
+    if (s < nw) base[(int64_t)k0 * nws + s] = buf[i];
   }
 }
 
@@ -366,14 +388,14 @@ k_wsticks_forward(cplx<T>* __restrict__ wst, int n0, int nw, FFTPlan P0,
 // F1(m) = (Z(m) + conj Z(-m)) / 2, F2(m) = (Z(m) - conj Z(-m)) / (2i), times scale.
 template <typename T>
 __global__ void k_extract_sphere(const cplx<T>* __restrict__ wst, int npt, int per_trial,
-                                 int n0, int nw, int npw, const int2* __restrict__ pos, T scale,
+                                 int n0, int nws, int npw, const int2* __restrict__ pos, T scale,
                                  T* __restrict__ coef) {
   const int pack = blockIdx.y;
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= npw) return;
   const int b = pack / npt, j = pack - b * npt;
   const int v1 = 2 * j, v2 = 2 * j + 1;
-  const cplx<T>* base = wst + (int64_t)pack * n0 * nw;
+  const cplx<T>* base = wst + (int64_t)pack * n0 * nws;
   const int2 ps = pos[h];
   const cplx<T> zp = base[ps.x], zm = base[ps.y];
   const T hs = T(0.5) * scale;
@@ -598,7 +620,7 @@ void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int 
   dim3 grid(g.nwtile, nb * npt);
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
   WTD_STICK_LAUNCH(k_sphere_to_wsticks, T, grid, lds, s, coef, per_trial, npt, npw, g.n0, g.nw,
-                   g.wtile_off, g.wtile_ent, g.plan0, static_cast<const cplx<T>*>(g.tw0), wst);
+                   g.nws, g.wtile_off, g.wtile_ent, g.plan0, static_cast<const cplx<T>*>(g.tw0), wst);
 }
 
 template <typename T>
@@ -609,11 +631,11 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   const int npt = (per_trial + 1) / 2;
   if (!drho || !part) ngroup = 1;
   ngroup = std::max(1, std::min(ngroup, npt));
-  dim3 grid(g.n0, nb * ngroup);
+  dim3 grid((unsigned)((g.n0 * nb * ngroup + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
   T* dtarget = (ngroup > 1) ? part : drho;
   WTD_PLANE_LAUNCH(k_wsticks_to_fields, T, grid, lds, s, wst, npt, per_trial, g.n0, g.n1, g.n2,
-                   g.nw, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), scale, out, phi, dtarget, ngroup, nb);
   if (ngroup > 1) {
     const int64_t n = (int64_t)nb * g.nr;
@@ -626,10 +648,10 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
 template <typename T>
 void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads, int npack,
                              int limit, cplx<T>* dst, hipStream_t s) {
-  dim3 grid(g.n0, npack);
+  dim3 grid((unsigned)((g.n0 * npack + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
-  WTD_PLANE_LAUNCH(k_pairs_to_dsticks, T, grid, lds, s, src, quads, limit, g.n0, g.n1, g.n2, g.nd,
-                   g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+  WTD_PLANE_LAUNCH(k_pairs_to_dsticks, T, grid, lds, s, src, quads, npack, limit, g.n0, g.n1,
+                   g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), dst);
 }
 
@@ -637,7 +659,7 @@ template <typename T>
 void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s) {
   dim3 grid((g.nd + kStickTile - 1) / kStickTile, npack);
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
-  WTD_STICK_LAUNCH(k_dstick_poisson, T, grid, lds, s, dst, g.n0, g.nd,
+  WTD_STICK_LAUNCH(k_dstick_poisson, T, grid, lds, s, dst, g.n0, g.nd, g.nds,
                    static_cast<const T*>(g.dkern), g.plan0, static_cast<const cplx<T>*>(g.tw0));
 }
 
@@ -647,7 +669,7 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
   dim3 grid(g.n0, npack);
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_dsticks_to_fields, T, grid, lds, s, dst, nfield, g.n0, g.n1, g.n2, g.nd,
-                   g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), out);
 }
 
@@ -659,7 +681,7 @@ void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int pe
   dim3 grid(g.n0, nb * npt);
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_fields_to_wsticks, T, grid, lds, s, fields, npt, per_trial, g.n0, g.n1, g.n2,
-                   g.nw, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), wst);
 }
 
@@ -667,7 +689,7 @@ template <typename T>
 void launch_wsticks_to_sphere(const Geometry& g, cplx<T>* wst, int npack, hipStream_t s) {
   dim3 grid((g.nw + kStickTile - 1) / kStickTile, npack);
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
-  WTD_STICK_LAUNCH(k_wsticks_forward, T, grid, lds, s, wst, g.n0, g.nw, g.plan0,
+  WTD_STICK_LAUNCH(k_wsticks_forward, T, grid, lds, s, wst, g.n0, g.nw, g.nws, g.plan0,
                    static_cast<const cplx<T>*>(g.tw0));
 }
 
@@ -677,7 +699,7 @@ void launch_extract_sphere(const Geometry& g, const cplx<T>* wst, int nb, int pe
   (void)nfield_per_trial;
   const int npt = (per_trial + 1) / 2;
   dim3 grid((npw + 255) / 256, nb * npt);
-  hipLaunchKernelGGL(k_extract_sphere<T>, grid, dim3(256), 0, s, wst, npt, per_trial, g.n0, g.nw,
+  hipLaunchKernelGGL(k_extract_sphere<T>, grid, dim3(256), 0, s, wst, npt, per_trial, g.n0, g.nws,
                      npw, g.sph_pos, scale, coef);
   WTD_HIP(hipGetLastError());
 }

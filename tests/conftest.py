@@ -10,7 +10,17 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long-running CPU test")
+    config.addinivalue_line(
+        "markers", "slow: minutes of oracle work; runs only with WTD_SLOW_TESTS=1")
+
+
+def pytest_collection_modifyitems(config, items):
+    if os.environ.get("WTD_SLOW_TESTS") == "1":
+        return
+    skip = pytest.mark.skip(reason="minutes of oracle work; set WTD_SLOW_TESTS=1 to run")
+    for item in items:
+        if "slow" in item.keywords:
+            item.add_marker(skip)
 
 
 @pytest.fixture(scope="session")
