@@ -78,6 +78,10 @@ CONFIGS = {
                  ncond=9, gap=0.2, nb=3, nroots=3, seed=12),
     "p3": Config("p3", *_cubic(13.5, 72), ecut_ry=40.0, nocc=36, ncond=20, gap=0.15,
                  nb=7, nroots=4, seed=13),
+    # Nocc = 128 with 16-trial blocks on a small grid (the eight-row-tile
+    # contraction at a size the oracle applies in seconds)
+    "p5": Config("p5", *_cubic(10.0, 24), ecut_ry=12.0, nocc=128, ncond=16, gap=0.15,
+                 nb=16, nroots=4, seed=15),
     # more than 128 occupied orbitals (row-blocked exchange: blocks 64, 64, 16)
     "p4": Config("p4", *_cubic(12.0, 36), ecut_ry=20.0, nocc=144, ncond=24, gap=0.15,
                  nb=3, nroots=3, seed=14),
@@ -229,7 +233,8 @@ def trials_in_span(sys: System, nb: int, seed: int | None = None):
     rng = np.random.default_rng(seed + 1000)
     x = rng.standard_normal((nb, sys.nocc, sys.ncond))
     x /= np.sqrt(np.sum(x * x, axis=(1, 2)))[:, None, None]
-    a = np.einsum("bvc,cm->bvm", x, sys.c_cond)
+    xf = x.reshape(-1, sys.ncond)
+    a = (xf @ sys.c_cond.real + 1j * (xf @ sys.c_cond.imag)).reshape(nb, sys.nocc, -1)
     return a, x
 
 

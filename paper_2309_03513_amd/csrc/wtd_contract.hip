@@ -271,6 +271,98 @@ __device__ __forceinline__ void tri_walk(typename Mfma<T>::acc_t (&acc)[CTile<T>
   }
 }
 
+// Grouped walk for full tiles: the column tiles J = I..NT-1 of row tile I are
+// taken G at a time.  A group's G tau tiles and G trial tiles are staged in LDS
+// together, and the next group's global loads are issued (into registers)
+// before the current group's MFMAs, so one memory latency is paid per group
+// rather than per tile.  The B' operands of a[I] come from slot 0 of the
+// first group of row I (J = I).
+template <int G>
+__device__ __forceinline__ bool next_group(int NT, int& I, int& J0) {
+  if (J0 + G < NT) {
+    J0 += G;
+    return true;
+  }
+  ++I;
+  J0 = I;
+  return I < NT;
+}
+
+template <typename T, int NT, int G>
+__device__ __forceinline__ void tri_walk_grouped(
+    typename Mfma<T>::acc_t (&acc)[CTile<T>::PPW][NT], T* s_tau, T* s_a,
+    const T* __restrict__ at, const T* __restrict__ tau, const CArgs& a) {
+  typedef CTile<T> C;
+  const int lx = a.lane & 15, ly = a.lane >> 4;
+  T pt[G][kPer<T>], pa[G][kPer<T>];
+  // loads of group (0, 0)
+#pragma unroll
+  for (int k = 0; k < G; ++k)
+    if (k < NT) {
+      fetch_tau(pt[k], tau, 0, k, a);
+      fetch_at(pa[k], at, k, a);
+    }
+  T bI[C::PPW][4];
+  int I = 0, J0 = 0;
+#pragma unroll 1
+  while (true) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+      if (J0 + k < NT) {
+        put_tile(s_tau + k * C::NE, pt[k]);
+        put_tile(s_a + k * C::NE, pa[k]);
+      }
+    __syncthreads();
+    const int Ic = I, J0c = J0;
+    const bool more = next_group<G>(NT, I, J0);
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+        if (J0 + k < NT) {
+          fetch_tau(pt[k], tau, I, J0 + k, a);
+          fetch_at(pa[k], at, J0 + k, a);
+        }
+    }
+    if (J0c == Ic) {
+#pragma unroll
+      for (int pp = 0; pp < C::PPW; ++pp)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          bI[pp][k] = s_a[C::at((4 * k + ly) * 16 + lx, a.wave * C::PPW + pp)];
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int J = J0c + k;
+      if (J < NT) {
+        const T* st = s_tau + k * C::NE;
+        const T* sa = s_a + k * C::NE;
+#pragma unroll
+        for (int pp = 0; pp < C::PPW; ++pp) {
+          const int p = a.wave * C::PPW + pp;
+          T x[4], y[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            x[q] = st[C::at(lx * 16 + 4 * q + ly, p)];
+            y[q] = sa[C::at((4 * q + ly) * 16 + lx, p)];
+          }
+          mfma_into<NT, T>(acc[pp], Ic, x, y);
+          if (J != Ic) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = st[C::at((4 * q + ly) * 16 + lx, p)];
+            mfma_into<NT, T>(acc[pp], J, x, bI[pp]);
+          }
+        }
+      }
+    }
+    if (!more) break;
+  }
+}
+
+// tiles staged together by the grouped walk
+template <typename T>
+constexpr int kGroup = 2;
+
 // R = c_K phi (v_H + f_xc drho) - alpha acc for row tile I, staged through LDS.
 template <typename T, int NT, int I>
 __device__ __forceinline__ void write_rows(const typename Mfma<T>::acc_t (&acc)[CTile<T>::PPW][NT],
@@ -321,8 +413,9 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
                 int k1d, T* __restrict__ R) {
   typedef CTile<T> C;
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T s_tau[C::NE];
-  __shared__ T s_a[C::NE];
+  constexpr int NG = FULL ? kGroup<T> : 1;
+  __shared__ T s_tau[NG * C::NE];
+  __shared__ T s_a[NG * C::NE];
   __shared__ int64_t s_rbnr[16 * NT];
   // XCD-aware order: each XCD takes a contiguous range of point tiles, so the
   // rows of neighbouring tiles are fetched through one L2.
@@ -352,10 +445,265 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
   for (int pp = 0; pp < C::PPW; ++pp)
 #pragma unroll
     for (int i = 0; i < NT; ++i) acc[pp][i] = acc_t{0, 0, 0, 0};
-  if (k1d) tri_walk<T, NT, FULL>(acc, s_tau, s_a, at, tau, a);
+  if (k1d) {
+    if constexpr (FULL)
+      tri_walk_grouped<T, NT, NG>(acc, s_tau, s_a, at, tau, a);
+    else
+      tri_walk<T, NT, FULL>(acc, s_tau, s_a, at, tau, a);
+  }
   const int64_t r = a.r0 + threadIdx.x % C::TP;
   const T fx = (r < nr && k1e) ? fxc[r] : T(0);
   write_rows<T, NT, 0>(acc, s_tau, phi, vh, drho, fx, ck, alpha, k1e, R, a);
+}
+
+// ---------------------------------------------------------------------------
+// Round-robin form for Nocc = 128 (eight row tiles), FP32, full tiles.
+//
+// Wave w owns row tile w: its accumulators hold R[w] (16 rows x 16 trials) for
+// all TP = 8 points of the workgroup, indexed at compile time, so the MFMA
+// chains of the eight points are independent.  The 36 tau tiles of the upper
+// triangle are visited in 8 rounds of a round-robin tournament: in round
+// r < 7 the row tiles pair up as {r, 7} and {(r + k) mod 7, (r - k) mod 7},
+// k = 1..3 (four off-diagonal tiles, each used by both of its waves, once
+// directly and once transposed); round 7 holds the eight diagonal tiles.
+// All eight trial tiles stay in LDS for the whole walk; the tau tiles of the
+// next round are fetched into registers while the current round computes.
+//
+// LDS tile layout: element (q, p) at p * 264 + perm(q), perm(q) =
+// q ^ (((q >> 6) & 3) << 2).  The point stride (264 = 8 mod 64 words) and the
+// permutation make the MFMA operand reads (fixed point, lanes over (lx, ly))
+// and the staging stores (lanes over 8 points x 8 pairs) each touch 64
+// distinct banks, and the eight points of one q are reached through
+// immediate offsets.
+struct RRTile {
+  static constexpr int TP = 8;
+  static constexpr int THREADS = 512;
+  static constexpr int PS = 264;            // point stride (words)
+  static constexpr int NE = PS * TP;        // words per tile
+  static constexpr int PER = 256 * TP / THREADS;  // tile elements staged per thread
+  static __device__ __forceinline__ int perm(int q) { return q ^ (((q >> 6) & 3) << 2); }
+  static __device__ __forceinline__ int at(int q, int p) { return p * PS + perm(q); }
+};
+
+// partner of row tile w in round r (r < 7), and the slot of the pair's tile
+__device__ __forceinline__ void rr_pair(int r, int w, int& partner, int& slot) {
+  if (w == 7 || w == r) {
+    partner = (w == 7) ? r : 7;
+    slot = 0;
+    return;
+  }
+  const int d = (w - r + 7) % 7;
+  partner = (2 * r - w + 14) % 7;
+  slot = d <= 3 ? d : 7 - d;
+}
+
+// (I, J), I < J, of slot `slot` in an off-diagonal round r < 7
+__device__ __forceinline__ void rr_tile(int r, int slot, int& I, int& J) {
+  int a, b;
+  if (slot == 0) {
+    a = r;
+    b = 7;
+  } else {
+    a = (r + slot) % 7;
+    b = (r - slot + 7) % 7;
+  }
+  I = min(a, b);
+  J = max(a, b);
+}
+
+// Per-thread constants of the tau staging: thread t stages point p = t % 8 and
+// combos c = g + 64 it (g = t / 8): row v_loc = (g >> 4) + 4 it, column w_loc = g & 15.
+struct RRLoad {
+  int64_t col;        // w_loc N_r + r: column offset of the off-diagonal tiles
+  int64_t dcol[4];    // max(v_loc, w_loc) N_r + r: diagonal tiles
+  int vrow[4];        // v_loc
+  int drow[4];        // min(v_loc, w_loc)
+};
+
+__device__ __forceinline__ void rr_fetch(float (&v)[8][RRTile::PER], const float* __restrict__ tau,
+                                         const int64_t* rbnr, const RRLoad& L, int r, int64_t nr) {
+  if (r < 7) {
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      int I, J;
+      rr_tile(r, sl, I, J);
+      const float* base = tau + (int64_t)J * 16 * nr + L.col;
+#pragma unroll
+      for (int it = 0; it < RRTile::PER; ++it) v[sl][it] = base[rbnr[I * 16 + L.vrow[it]]];
+    }
+  } else {
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      const float* base = tau + (int64_t)sl * 16 * nr;
+#pragma unroll
+      for (int it = 0; it < RRTile::PER; ++it)
+        v[sl][it] = base[rbnr[sl * 16 + L.drow[it]] + L.dcol[it]];
+    }
+  }
+}
+
+__device__ __forceinline__ void rr_put(float* s_t, const float (&v)[8][RRTile::PER], int r) {
+  const int p = threadIdx.x % RRTile::TP;
+  const int g = threadIdx.x / RRTile::TP;
+  const int ntl = (r == 7) ? 8 : 4;
+#pragma unroll
+  for (int sl = 0; sl < 8; ++sl)
+    if (sl < ntl) {
+#pragma unroll
+      for (int it = 0; it < RRTile::PER; ++it)
+        s_t[sl * RRTile::NE + RRTile::at(g + it * (RRTile::THREADS / RRTile::TP), p)] = v[sl][it];
+    }
+}
+
+__global__ void __launch_bounds__(RRTile::THREADS)
+k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ phi,
+              const float* __restrict__ at, const float* __restrict__ tau,
+              const float* __restrict__ vh, const float* __restrict__ drho,
+              const float* __restrict__ fxc, float ck, float alpha, int k1e, int k1d,
+              float* __restrict__ R) {
+  typedef RRTile C;
+  typedef Mfma<float>::acc_t acc_t;
+  __shared__ float s_a[8 * C::NE];   // trial tiles a~[b0 + b][16 K + v'], K = 0..7
+  __shared__ float s_t[8 * C::NE];   // tau tiles of one round; reused to stage R
+  __shared__ int64_t s_rbnr[128];    // pair (v, w >= v) starts at s_rbnr[v] + w N_r
+  const int per = (ntile + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntile) return;
+  const int b0 = blockIdx.y * 16;
+  const int64_t r0 = (int64_t)tile * C::TP;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lx = lane & 15, ly = lane >> 4;
+  const int p_ld = threadIdx.x % C::TP;
+  const int g_ld = threadIdx.x / C::TP;
+  const int64_t rp = r0 + p_ld;
+  for (int v = threadIdx.x; v < 128; v += blockDim.x)
+    s_rbnr[v] = ((int64_t)v * nocc - (int64_t)v * (v + 1) / 2) * nr;
+
+  acc_t acc[C::TP];
+#pragma unroll
+  for (int p = 0; p < C::TP; ++p) acc[p] = acc_t{0, 0, 0, 0};
+
+  // response-term inputs of this thread's output elements, loaded during the
+  // last rounds: phi[16 K + v_loc][r], v_H[b][r], drho[b][r], f_xc[r]
+  float ph[8][C::PER];
+  float vhb = 0.f, drb = 0.f, fx = 0.f;
+  auto load_response = [&]() {
+    if (k1e) {
+      const int b = b0 + (g_ld & 15);
+#pragma unroll
+      for (int K = 0; K < 8; ++K)
+#pragma unroll
+        for (int it = 0; it < C::PER; ++it)
+          ph[K][it] = phi[(int64_t)(K * 16 + (g_ld >> 4) + 4 * it) * nr + rp];
+      vhb = vh[(int64_t)b * nr + rp];
+      drb = drho[(int64_t)b * nr + rp];
+      fx = fxc[rp];
+    }
+  };
+
+  if (k1d) {
+    RRLoad L;
+    {
+      const int wl = g_ld & 15;
+      L.col = (int64_t)wl * nr + rp;
+#pragma unroll
+      for (int it = 0; it < C::PER; ++it) {
+        const int vl = (g_ld >> 4) + 4 * it;
+        L.vrow[it] = vl;
+        L.drow[it] = min(vl, wl);
+        L.dcol[it] = (int64_t)max(vl, wl) * nr + rp;
+      }
+    }
+    // tau tiles of three rounds in flight (the memory latency under load spans
+    // several rounds of MFMA work)
+    float vb[3][8][C::PER];
+    {
+      float ta[8][C::PER];
+#pragma unroll
+      for (int K = 0; K < 8; ++K)
+#pragma unroll
+        for (int it = 0; it < C::PER; ++it) {
+          const int c = g_ld + it * (C::THREADS / C::TP);
+          ta[K][it] = at[((int64_t)(b0 + (c & 15)) * nocc + K * 16 + (c >> 4)) * nr + rp];
+        }
+      __syncthreads();  // s_rbnr
+#pragma unroll
+      for (int r = 0; r < 3; ++r) rr_fetch(vb[r], tau, s_rbnr, L, r, nr);
+#pragma unroll
+      for (int K = 0; K < 8; ++K)
+#pragma unroll
+        for (int it = 0; it < C::PER; ++it)
+          s_a[K * C::NE + C::at(g_ld + it * (C::THREADS / C::TP), p_ld)] = ta[K][it];
+    }
+    // lane-constant LDS offsets of the MFMA operands for K-step s4:
+    // direct A[m = lx][k = 4 s4 + ly] = tau[v = lx][w = 4 s4 + ly];
+    // transposed A = tau[v = 4 s4 + ly][w = lx]; B[k = v'][n = b] = a~[4 s4 + ly][lx]
+    int oa_d[4], oa_t[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      oa_d[s4] = C::perm(lx * 16 + 4 * s4 + ly);
+      oa_t[s4] = C::perm((4 * s4 + ly) * 16 + lx);
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      __syncthreads();
+      rr_put(s_t, vb[r % 3], r);
+      __syncthreads();
+      if (r + 3 < 8) rr_fetch(vb[r % 3], tau, s_rbnr, L, r + 3, nr);
+      if (r == 5) load_response();
+      int partner, slot;
+      if (r < 7) {
+        rr_pair(r, w, partner, slot);
+      } else {
+        partner = w;
+        slot = w;
+      }
+      const float* st = s_t + slot * C::NE;
+      const float* sa = s_a + partner * C::NE;
+      const bool direct = w <= partner;
+      // operands of K-step s4 for the eight points, loaded one step ahead
+      float xa[2][C::TP], xb[2][C::TP];
+#pragma unroll
+      for (int s4 = 0; s4 < 5; ++s4) {
+        if (s4 < 4) {
+          const float* pa = st + (direct ? oa_d[s4] : oa_t[s4]);
+          const float* pb = sa + oa_t[s4];
+#pragma unroll
+          for (int p = 0; p < C::TP; ++p) {
+            xa[s4 & 1][p] = pa[p * C::PS];
+            xb[s4 & 1][p] = pb[p * C::PS];
+          }
+        }
+        if (s4 > 0) {
+#pragma unroll
+          for (int p = 0; p < C::TP; ++p)
+            acc[p] = Mfma<float>::run(xa[(s4 - 1) & 1][p], xb[(s4 - 1) & 1][p], acc[p]);
+        }
+      }
+    }
+  } else {
+    load_response();
+  }
+
+  // R[b][16 w + row] = -alpha acc (+ c_K phi (v_H + f_xc drho)), staged through LDS
+  __syncthreads();
+  float* so = s_t + w * C::NE;
+#pragma unroll
+  for (int p = 0; p < C::TP; ++p)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) so[C::at(Mfma<float>::row(lane, e) * 16 + lx, p)] = acc[p][e];
+  __syncthreads();
+  const float vb_resp = vhb + fx * drb;
+#pragma unroll
+  for (int K = 0; K < 8; ++K)
+#pragma unroll
+    for (int it = 0; it < C::PER; ++it) {
+      const int c = g_ld + it * (C::THREADS / C::TP);
+      const int v = K * 16 + (c >> 4), b = b0 + (c & 15);
+      float val = -alpha * s_t[K * C::NE + C::at(c, p_ld)];
+      if (k1e) val += ck * ph[K][it] * vb_resp;
+      R[((int64_t)b * nocc + v) * nr + rp] = val;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -518,6 +866,20 @@ bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, con
                           bool k1e, bool k1d, T* R, hipStream_t s) {
   const int nt = (nocc + 15) / 16;
   if (nt > 8) return false;
+  if constexpr (sizeof(T) == 4) {
+    if (nocc == 128 && nb % 16 == 0 && g.nr % RRTile::TP == 0) {
+      const int64_t nt64 = g.nr / RRTile::TP;
+      WTD_REQUIRE(nt64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
+      const int ntile = (int)nt64;
+      dim3 grid(8 * ((ntile + 7) / 8), nb / 16);
+      hipLaunchKernelGGL(k_contract_rr, grid, dim3(RRTile::THREADS), 0, s, nb, nocc, g.nr, ntile,
+                         (const float*)phi, (const float*)at, (const float*)tau, (const float*)vh,
+                         (const float*)drho, (const float*)fxc, (float)ck, (float)alpha, (int)k1e,
+                         (int)k1d, (float*)R);
+      WTD_HIP(hipGetLastError());
+      return true;
+    }
+  }
   typedef CTile<T> C;
   const int64_t ntile64 = (g.nr + C::TP - 1) / C::TP;
   WTD_REQUIRE(ntile64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");

@@ -53,6 +53,22 @@ def test_apply_72cubed_fp64(systems):
         assert err <= 1e-10
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_apply_nocc128_nb16(systems, prec, tol):
+    """Nocc = 128, Nb = 16 on a 24^3 grid: the eight-row-tile contraction of
+    the benchmark workload, compared element by element."""
+    s = systems("p5")
+    a = trials_random(s, 16)
+    for term in ("K1D", "ALL"):
+        say(f"apply {prec} cfg=p5 (Nocc=128, Nb=16) term={term}")
+        L = _ctx(s, 16, prec, TERMS[term])
+        got = to_complex(L.apply(a))
+        L.close()
+        err = rel_err(got, oracle.apply_liouville(s, a, terms=TERMS[term]))
+        say(f"  rel err {err:.3e}")
+        assert err <= tol
+
+
 @pytest.mark.parametrize("cfg", ["c1", "p1", "p3"])
 def test_apply_fp32(systems, cfg):
     s = systems(cfg)
