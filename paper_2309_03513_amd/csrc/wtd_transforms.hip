@@ -25,6 +25,14 @@ namespace {
 
 constexpr int kStickThreads = 256;
 constexpr int kPlaneThreads = 512;
+constexpr int kPairItems = 4;  // (plane, pack) items per workgroup of the prefetching pair kernel
+
+// items per workgroup of the pair-product kernel: kPairItems for FP64 planes up
+// to 72 x 72 (compile-time plans), one otherwise
+template <int SN, typename T>
+constexpr int pair_items() {
+  return (SN > 0 && SN * SN <= 72 * 72 && sizeof(T) == 8) ? kPairItems : 1;
+}
 
 int min_radix(const FFTPlan& p) {
   int r = 8;
@@ -236,30 +244,107 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* twl = pl + plane;
+  const int64_t nr = (int64_t)n0 * plane;
   // item = (i0, pack), pack fastest: an XCD works through its planes one at a
   // time, so the orbital planes of the current i0 stay in its L2
-  const int item = xcd_item(n0 * npack);
-  if (item < 0) return;
-  stage_twiddles<SN>(twl, tw1);
-  const int i0 = item / npack;
-  const int pack = item - i0 * npack;
-  const int64_t nr = (int64_t)n0 * plane;
-  const int64_t poff = (int64_t)i0 * plane;
-  int4 q = quads[pack];
-  if (q.z >= limit) q.z = -1;  // packs past the last valid field carry no imaginary part
-  const T* fa = src + (int64_t)q.x * nr + poff;
-  const T* fb = q.y >= 0 ? src + (int64_t)q.y * nr + poff : nullptr;
-  const T* fc = q.z >= 0 ? src + (int64_t)q.z * nr + poff : nullptr;
-  const T* fd = q.w >= 0 ? src + (int64_t)q.w * nr + poff : nullptr;
-  for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-    T re = fb ? fa[i] * fb[i] : fa[i];
-    T im = fc ? (fd ? fc[i] * fd[i] : fc[i]) : T(0);
-    pl[i] = {re, im};
+  const int total = n0 * npack;
+  if constexpr (pair_items<SN, T>() > 1) {
+    // kPairItems consecutive items per workgroup; the four orbital planes of
+    // the next item are loaded into registers while the current one is
+    // transformed (FP64: one workgroup per CU fits the LDS, so the latency of
+    // the next item's loads is hidden by prefetch instead of by other
+    // workgroups; FP32 keeps one item per workgroup and three workgroups per CU)
+    constexpr int PL = SN * SN;
+    constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
+    const int grp = xcd_item((total + kPairItems - 1) / kPairItems);
+    if (grp < 0) return;
+    stage_twiddles<SN>(twl, tw1);
+    const int it0 = grp * kPairItems, it1 = min(total, it0 + kPairItems);
+    T ra[EL], rb[EL], rc[EL], rd[EL];
+    auto load = [&](int item) {
+      const int i0 = item / npack;
+      const int pack = item - i0 * npack;
+      const int64_t poff = (int64_t)i0 * plane;
+      int4 q = quads[pack];
+      if (q.z >= limit) q.z = -1;  // packs past the last valid field carry no imaginary part
+      const T* fa = src + (int64_t)q.x * nr + poff;
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) ra[e] = fa[i];
+      }
+      if (q.y >= 0) {
+        const T* fb = src + (int64_t)q.y * nr + poff;
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+          const int i = threadIdx.x + e * kPlaneThreads;
+          if (PL % kPlaneThreads == 0 || i < PL) rb[e] = fb[i];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EL; ++e) rb[e] = T(1);
+      }
+      if (q.z >= 0) {
+        const T* fc = src + (int64_t)q.z * nr + poff;
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+          const int i = threadIdx.x + e * kPlaneThreads;
+          if (PL % kPlaneThreads == 0 || i < PL) rc[e] = fc[i];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EL; ++e) rc[e] = T(0);
+      }
+      if (q.z >= 0 && q.w >= 0) {
+        const T* fd = src + (int64_t)q.w * nr + poff;
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+          const int i = threadIdx.x + e * kPlaneThreads;
+          if (PL % kPlaneThreads == 0 || i < PL) rd[e] = fd[i];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EL; ++e) rd[e] = T(1);
+      }
+    };
+    load(it0);
+    for (int item = it0; item < it1; ++item) {
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) pl[i] = {ra[e] * rb[e], rc[e] * rd[e]};
+      }
+      __syncthreads();
+      if (item + 1 < it1) load(item + 1);
+      plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+      const int i0 = item / npack;
+      const int pack = item - i0 * npack;
+      cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nds;
+      for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
+      __syncthreads();
+    }
+  } else {
+    const int item = xcd_item(total);
+    if (item < 0) return;
+    const int i0 = item / npack;
+    const int pack = item - i0 * npack;
+    const int64_t poff = (int64_t)i0 * plane;
+    int4 q = quads[pack];
+    if (q.z >= limit) q.z = -1;  // packs past the last valid field carry no imaginary part
+    const T* fa = src + (int64_t)q.x * nr + poff;
+    const T* fb = q.y >= 0 ? src + (int64_t)q.y * nr + poff : nullptr;
+    const T* fc = q.z >= 0 ? src + (int64_t)q.z * nr + poff : nullptr;
+    const T* fd = q.w >= 0 ? src + (int64_t)q.w * nr + poff : nullptr;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      T re = fb ? fa[i] * fb[i] : fa[i];
+      T im = fc ? (fd ? fc[i] * fd[i] : fc[i]) : T(0);
+      pl[i] = {re, im};
+    }
+    __syncthreads();
+    plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+    cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nds;
+    for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
   }
-  __syncthreads();
-  plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nds;
-  for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
 }
 
 // ---------------------------------------------------------------- Poisson on density sticks
@@ -648,7 +733,10 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
 template <typename T>
 void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads, int npack,
                              int limit, cplx<T>* dst, hipStream_t s) {
-  dim3 grid((unsigned)((g.n0 * npack + 7) / 8 * 8));
+  const int ps = plane_static(g);
+  const int per_wg = (ps > 0 && ps * ps <= 72 * 72 && sizeof(T) == 8) ? kPairItems : 1;
+  const int ngrp = (g.n0 * npack + per_wg - 1) / per_wg;
+  dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_pairs_to_dsticks, T, grid, lds, s, src, quads, npack, limit, g.n0, g.n1,
                    g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
