@@ -326,6 +326,7 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
   } else {
     const int item = xcd_item(total);
     if (item < 0) return;
+    stage_twiddles<SN>(twl, tw1);
     const int i0 = item / npack;
     const int pack = item - i0 * npack;
     const int64_t poff = (int64_t)i0 * plane;
