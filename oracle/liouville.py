@@ -46,15 +46,17 @@ TERM_K1D = 4
 TERM_ALL = 7
 
 
-def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None):
+def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None, progress=None):
     """la = L a for a trial block a [nb][nocc][npw] (complex half-sphere coefficients).
 
     ``s`` carries cell, n, mill, c_occ, c_cond, eps_occ, eps_cond, fxc, alpha,
     c_k and v_g0.  ``rows`` restricts the output to a list of occupied indices
     v (the result then has shape [nb][len(rows)][npw]); the sum over v' always
     runs over every occupied orbital.  ``occ`` overrides the occupied
-    coefficients (used by the rotation-invariance check).
+    coefficients (used by the rotation-invariance check).  ``progress``, if
+    given, is called with a short message as each step completes.
     """
+    say = progress if progress is not None else (lambda msg: None)
     a = np.asarray(a, dtype=np.complex128)
     cell, n, mill = np.asarray(s.cell, dtype=np.float64), tuple(s.n), s.mill
     c_occ = s.c_occ if occ is None else occ
@@ -78,6 +80,7 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None)
     # step 2: real space
     phi = real_space(c_occ, mill, cell, n)                                  # [nocc][n]
     at = real_space(a_t, mill, cell, n)                                     # [nb][nocc][n]
+    say("oracle: orbitals and projected trials on the grid")
 
     # steps 3-4: density response and its Hartree + f_xc potential
     V = None
@@ -85,6 +88,7 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None)
         kern = coulomb_kernel(cell, n, s.v_g0)
         drho = np.stack([np.einsum("vxyz,vxyz->xyz", phi, at[b]) for b in range(nb)])
         V = s.c_k * (poisson(drho, kern) + s.fxc[None] * drho)
+        say("oracle: density response potential")
 
     # steps 5-6: R_v(r) for the requested rows
     R = np.zeros((nb, len(rows)) + n)
@@ -97,6 +101,7 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None)
             tau = poisson(phi[v][None] * phi, kern)                         # [nocc][n]
             for b in range(nb):
                 R[b, i] -= s.alpha * np.einsum("uxyz,uxyz->xyz", tau, at[b])
+            say(f"oracle: exchange for row {v}")
 
     # step 7: back to the projected plane-wave space
     if projector == "span":

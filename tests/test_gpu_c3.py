@@ -27,9 +27,10 @@ def c3_case(systems):
     s = systems("c3")
     a = trials_random(s, 2)
     say("oracle rows at 108^3 / Nocc = 432: exchange + D")
-    ref_d_k1d = oracle.apply_liouville(s, a, terms=oracle.TERM_D | oracle.TERM_K1D, rows=ROWS)
+    ref_d_k1d = oracle.apply_liouville(s, a, terms=oracle.TERM_D | oracle.TERM_K1D, rows=ROWS,
+                                       progress=say)
     say("oracle rows at 108^3 / Nocc = 432: response term")
-    ref_k1e = oracle.apply_liouville(s, a, terms=oracle.TERM_K1E, rows=ROWS)
+    ref_k1e = oracle.apply_liouville(s, a, terms=oracle.TERM_K1E, rows=ROWS, progress=say)
     return s, a, ref_d_k1d, ref_k1e
 
 
