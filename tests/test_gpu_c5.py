@@ -40,7 +40,8 @@ def c5(systems):
     L = _ctx(s, 16, "fp64")
     ga, go = L.apply_bwd(a, g)
     ga, go = to_complex(ga), to_complex(go)
-    return s, a, g, d_occ, d_a, L, ga, go
+    yield s, a, g, d_occ, d_a, L, ga, go
+    L.close()
 
 
 def test_c5_occ_gradient_vs_central_difference(c5):
@@ -79,6 +80,3 @@ def test_c5_fp32_backward_vs_fp64(c5):
     say(f"  rel err vs fp64: g_a {ea:.3e}, g_occ {eo:.3e}")
     assert ea <= 1e-4 and eo <= 1e-4
 
-
-def test_c5_close(c5):
-    c5[5].close()
