@@ -187,6 +187,64 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   const int64_t poff = (int64_t)i0 * plane;
   if (drho)
     for (int i = threadIdx.x; i < plane; i += blockDim.x) acc[i] = T(0);
+  if constexpr (SN == 72) {
+    // the next pack's sticks and the current pack's orbital planes are loaded
+    // into registers before the plane FFT, so their latency overlaps it
+    constexpr int PL = SN * SN;
+    constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
+    constexpr int WS = 2;  // wave sticks per thread (nw <= WS * kPlaneThreads, host-checked)
+    cplx<T> sv[WS];
+    int kv[WS];
+#pragma unroll
+    for (int e = 0; e < WS; ++e) {
+      const int st = threadIdx.x + e * kPlaneThreads;
+      kv[e] = st < nw ? k12[st] : -1;
+    }
+    auto load_sticks = [&](int j) {
+      const cplx<T>* src = wst + ((int64_t)(b * npt + j) * n0 + i0) * nws;
+#pragma unroll
+      for (int e = 0; e < WS; ++e)
+        if (kv[e] >= 0) sv[e] = src[threadIdx.x + e * kPlaneThreads];
+    };
+    if (j0 < j1) load_sticks(j0);
+    for (int j = j0; j < j1; ++j) {
+      for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < WS; ++e)
+        if (kv[e] >= 0) pl[kv[e]] = sv[e];
+      __syncthreads();
+      if (j + 1 < j1) load_sticks(j + 1);
+      const int v1 = 2 * j, v2 = 2 * j + 1;
+      const bool has2 = v2 < per_trial;
+      T f1[EL], f2[EL];
+      if (drho) {
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+          const int i = threadIdx.x + e * kPlaneThreads;
+          if (PL % kPlaneThreads == 0 || i < PL) {
+            f1[e] = phi[(int64_t)v1 * nr + poff + i];
+            f2[e] = has2 ? phi[(int64_t)v2 * nr + poff + i] : T(0);
+          }
+        }
+      }
+      plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+      T* o1 = out + ((int64_t)b * per_trial + v1) * nr + poff;
+      T* o2 = o1 + nr;
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) {
+          const cplx<T> z = pl[i];
+          const T a = z.x * scale, c = z.y * scale;
+          o1[i] = a;
+          if (has2) o2[i] = c;
+          if (drho) acc[i] += f1[e] * a + f2[e] * c;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
   for (int j = j0; j < j1; ++j) {
     const int pack = b * npt + j;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
@@ -211,6 +269,7 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
       }
     }
     __syncthreads();
+  }
   }
   if (drho) {
     T* d = drho + ((int64_t)grp * nbtot + b) * nr + poff;
@@ -717,6 +776,8 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   const int npt = (per_trial + 1) / 2;
   if (!drho || !part) ngroup = 1;
   ngroup = std::max(1, std::min(ngroup, npt));
+  WTD_REQUIRE(plane_static(g) != 72 || g.nw <= 2 * kPlaneThreads, WTD_ERR_SHAPE,
+              "too many wave sticks for the 72 x 72 plane kernel");
   dim3 grid((unsigned)((g.n0 * nb * ngroup + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
   T* dtarget = (ngroup > 1) ? part : drho;
