@@ -159,8 +159,11 @@ k_sphere_to_wsticks(const T* __restrict__ coef, int per_trial, int npt, int npw,
 // ---------------------------------------------------------------- sticks -> real fields
 // One workgroup per (i0, trial b); loops over the packs of that trial.  With
 // drho != nullptr also forms drho_b = sum_v phi_v out_bv on the plane.
+// (FP32 on 72 x 72 planes: capped at 128 registers so two workgroups share a CU,
+// as the LDS allows)
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
+__attribute__((amdgpu_waves_per_eu((SN == 72 && sizeof(T) == 4) ? 4 : 1)))
 k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int n0, int n1,
                     int n2, int nw, int nws, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
                     const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2, T scale,
@@ -477,29 +480,80 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
 }
 
 // ---------------------------------------------------------------- real fields -> wave sticks
+// Items (plane i0, pack) in XCD-contiguous ranges, `items` consecutive items per
+// workgroup; on 72 x 72 planes the next item's two fields are loaded into
+// registers while the current plane is transformed.
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
-k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int n0, int n1, int n2,
-                    int nw, int nws, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
-                    const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
-                    cplx<T>* __restrict__ wst) {
+k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int items, int n0,
+                    int n1, int n2, int nw, int nws, const int* __restrict__ k12, FFTPlan P1,
+                    FFTPlan P2, const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+                    cplx<T>* __restrict__ wst, int npack) {
   extern __shared__ unsigned char smem_raw[];
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int i0 = blockIdx.x;
-  const int pack = blockIdx.y;
-  const int b = pack / npt, j = pack - b * npt;
-  const int v1 = 2 * j, v2 = 2 * j + 1;
-  const int64_t nr = (int64_t)n0 * plane;
-  const T* f1 = fields + ((int64_t)b * per_trial + v1) * nr + (int64_t)i0 * plane;
-  const T* f2 = (v2 < per_trial) ? f1 + nr : nullptr;
   cplx<T>* twl = pl + plane;
+  const int64_t nr = (int64_t)n0 * plane;
+  const int total = n0 * npack;
+  const int grp = xcd_item((total + items - 1) / items);
+  if (grp < 0) return;
   stage_twiddles<SN>(twl, tw1);
-  for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {f1[i], f2 ? f2[i] : T(0)};
-  __syncthreads();
-  plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nws;
-  for (int s = threadIdx.x; s < nw; s += blockDim.x) o[s] = pl[k12[s]];
+  const int it0 = grp * items, it1 = min(total, it0 + items);
+  // item -> the pack's two fields at plane i0 (f2 = nullptr for an odd last orbital)
+  auto fields_of = [&](int item, const T*& f1, const T*& f2, int& i0, int& pack) {
+    i0 = item / npack;
+    pack = item - i0 * npack;
+    const int b = pack / npt, j = pack - b * npt;
+    const int v1 = 2 * j, v2 = 2 * j + 1;
+    f1 = fields + ((int64_t)b * per_trial + v1) * nr + (int64_t)i0 * plane;
+    f2 = (v2 < per_trial) ? f1 + nr : nullptr;
+  };
+  auto finish = [&](int i0, int pack) {
+    plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+    cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nws;
+    for (int st = threadIdx.x; st < nw; st += blockDim.x) o[st] = pl[k12[st]];
+  };
+  if constexpr (SN == 72) {
+    constexpr int PL = SN * SN;
+    constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
+    T r1[EL], r2[EL];
+    auto load = [&](int item) {
+      const T *f1, *f2;
+      int i0, pack;
+      fields_of(item, f1, f2, i0, pack);
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) {
+          r1[e] = f1[i];
+          r2[e] = f2 ? f2[i] : T(0);
+        }
+      }
+    };
+    load(it0);
+    for (int item = it0; item < it1; ++item) {
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) pl[i] = {r1[e], r2[e]};
+      }
+      __syncthreads();
+      if (item + 1 < it1) load(item + 1);
+      const int i0 = item / npack;
+      finish(i0, item - i0 * npack);
+      __syncthreads();
+    }
+  } else {
+    for (int item = it0; item < it1; ++item) {
+      const T *f1, *f2;
+      int i0, pack;
+      fields_of(item, f1, f2, i0, pack);
+      for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {f1[i], f2 ? f2[i] : T(0)};
+      __syncthreads();
+      finish(i0, pack);
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------- wave sticks: forward along i0
@@ -828,11 +882,15 @@ void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int pe
                               int nfield_per_trial, cplx<T>* wst, hipStream_t s) {
   (void)nfield_per_trial;
   const int npt = (per_trial + 1) / 2;
-  dim3 grid(g.n0, nb * npt);
+  const int npack = nb * npt;
+  const int items = plane_static(g) == 72 ? kPairItems : 1;
+  const int ngrp = (g.n0 * npack + items - 1) / items;
+  dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
-  WTD_PLANE_LAUNCH(k_fields_to_wsticks, T, grid, lds, s, fields, npt, per_trial, g.n0, g.n1, g.n2,
-                   g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
-                   static_cast<const cplx<T>*>(g.tw2), wst);
+  WTD_PLANE_LAUNCH(k_fields_to_wsticks, T, grid, lds, s, fields, npt, per_trial, items, g.n0,
+                   g.n1, g.n2, g.nw, g.nws, g.wst_k12, g.plan1, g.plan2,
+                   static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2), wst,
+                   npack);
 }
 
 template <typename T>
