@@ -416,34 +416,75 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
 template <int MB, int SN, typename T>
 __global__ void __launch_bounds__(kStickThreads)
 k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, int nds, const T* __restrict__ kern,
-                 FFTPlan P0, const cplx<T>* __restrict__ tw0) {
+                 FFTPlan P0, const cplx<T>* __restrict__ tw0, int ntile, int npack, int items) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int tile = blockIdx.x;
-  const int pack = blockIdx.y;
-  cplx<T>* base = dst + (int64_t)pack * n0 * nds;
   const int tot = n0 * kStickTile;
   cplx<T>* twl = buf + tot;
+  // items (pack, tile), tile fastest, `items` consecutive ones per workgroup in
+  // XCD-contiguous ranges
+  const int total = ntile * npack;
+  const int grp = xcd_item((total + items - 1) / items);
+  if (grp < 0) return;
   stage_twiddles<SN>(twl, tw0);
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    const int i0 = i / kStickTile, l = i - i0 * kStickTile;
-    const int s = tile * kStickTile + l;
-    buf[i] = (s < nd) ? base[(int64_t)i0 * nds + s] : cplx<T>{T(0), T(0)};
-  }
-  __syncthreads();
-  stick_fft<-1, SN, MB>(buf, P0, tw0, twl);
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    const int k0 = i / kStickTile, l = i - k0 * kStickTile;
-    const int s = tile * kStickTile + l;
-    const T kv = (s < nd) ? kern[(int64_t)s * n0 + k0] : T(0);
-    buf[i] = cscale(buf[i], kv);
-  }
-  __syncthreads();
-  stick_fft<+1, SN, MB>(buf, P0, tw0, twl);
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    const int i0 = i / kStickTile, l = i - i0 * kStickTile;
-    const int s = tile * kStickTile + l;
-    if (s < nd) base[(int64_t)i0 * nds + s] = buf[i];
+  const int it0 = grp * items, it1 = min(total, it0 + items);
+  auto transform = [&](int tile, cplx<T>* base) {
+    stick_fft<-1, SN, MB>(buf, P0, tw0, twl);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+      const int k0 = i / kStickTile, l = i - k0 * kStickTile;
+      const int s = tile * kStickTile + l;
+      const T kv = (s < nd) ? kern[(int64_t)s * n0 + k0] : T(0);
+      buf[i] = cscale(buf[i], kv);
+    }
+    __syncthreads();
+    stick_fft<+1, SN, MB>(buf, P0, tw0, twl);
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+      const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+      const int s = tile * kStickTile + l;
+      if (s < nd) base[(int64_t)i0 * nds + s] = buf[i];
+    }
+  };
+  if constexpr (SN > 0) {
+    // the next tile's sticks are loaded into registers while this one is transformed
+    constexpr int EL = (SN * kStickTile + kStickThreads - 1) / kStickThreads;
+    cplx<T> rv[EL];
+    auto load = [&](int item) {
+      const int pack = item / ntile, tile = item - pack * ntile;
+      const cplx<T>* base = dst + (int64_t)pack * n0 * nds;
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kStickThreads;
+        const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+        const int s = tile * kStickTile + l;
+        rv[e] = (i < tot && s < nd) ? base[(int64_t)i0 * nds + s] : cplx<T>{T(0), T(0)};
+      }
+    };
+    load(it0);
+    for (int item = it0; item < it1; ++item) {
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kStickThreads;
+        if (i < tot) buf[i] = rv[e];
+      }
+      __syncthreads();
+      if (item + 1 < it1) load(item + 1);
+      const int pack = item / ntile, tile = item - pack * ntile;
+      transform(tile, dst + (int64_t)pack * n0 * nds);
+      __syncthreads();
+    }
+  } else {
+    for (int item = it0; item < it1; ++item) {
+      const int pack = item / ntile, tile = item - pack * ntile;
+      cplx<T>* base = dst + (int64_t)pack * n0 * nds;
+      for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int i0 = i / kStickTile, l = i - i0 * kStickTile;
+        const int s = tile * kStickTile + l;
+        buf[i] = (s < nd) ? base[(int64_t)i0 * nds + s] : cplx<T>{T(0), T(0)};
+      }
+      __syncthreads();
+      transform(tile, base);
+      __syncthreads();
+    }
   }
 }
 
@@ -861,10 +902,16 @@ void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads,
 
 template <typename T>
 void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s) {
-  dim3 grid((g.nd + kStickTile - 1) / kStickTile, npack);
+  const int ntile = (g.nd + kStickTile - 1) / kStickTile;
+  // several tiles per workgroup with prefetch pays off for FP32 (for FP64 the
+  // larger register footprint costs more occupancy than the prefetch gains)
+  const int items = (static_size(g.n0) && sizeof(T) == 4) ? kPairItems : 1;
+  const int ngrp = (ntile * npack + items - 1) / items;
+  dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
   WTD_STICK_LAUNCH(k_dstick_poisson, T, grid, lds, s, dst, g.n0, g.nd, g.nds,
-                   static_cast<const T*>(g.dkern), g.plan0, static_cast<const cplx<T>*>(g.tw0));
+                   static_cast<const T*>(g.dkern), g.plan0, static_cast<const cplx<T>*>(g.tw0),
+                   ntile, npack, items);
 }
 
 template <typename T>
