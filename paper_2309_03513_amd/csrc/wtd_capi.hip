@@ -498,8 +498,10 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->drho = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->drho_part = dalloc(c, (size_t)kDrhoGroups * mnb * nr * sizeof(T));
+  // (all pairs: rounded up to whole groups of 8 for the interleaved layout)
   const size_t tau_fields =
-      c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs) : c->npairs;
+      c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs)
+                   : ((size_t)c->npairs + 7) / 8 * 8;
   if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D))
     c->tau = dalloc(c, tau_fields * nr * sizeof(T));
   c->wst = dalloc(c, nwp * c->g.n0 * c->g.nws * sizeof(cplx<T>));
@@ -508,6 +510,8 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   int chunk = 512;
   if (const char* e = std::getenv("WTD_PAIR_CHUNK")) chunk = std::max(1, std::atoi(e));
   c->pair_chunk = std::max(1, std::min(c->npack_pairs, chunk));
+  // chunks start on whole groups of 8 fields (4 packs) for the interleaved layout
+  if (c->pair_chunk >= 4) c->pair_chunk = c->pair_chunk / 4 * 4;
   if (c->row_block)
     c->pair_chunk = std::min(c->pair_chunk, (int)((tau_fields + 1) / 2));
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
@@ -591,8 +595,13 @@ void apply_core(wtd_ctx* c, int nb) {
       }
     }
   }
-  // 5. pair potentials, in chunks of packed pairs
+  // 5. pair potentials, in chunks of packed pairs; stored interleaved by groups
+  // of kTauIl pairs when the round-robin contraction reads them (a chunk starts
+  // on a whole group, so its groups start at field 2 p0 in either layout)
+  const bool il = contract_rr_applies<T>(g, nb, nocc);
   if (k1d && !c->row_block) {
+    WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
+                WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
     for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
       const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
       const int nf = std::min(2 * np, c->npairs - 2 * p0);
@@ -603,7 +612,7 @@ void apply_core(wtd_ctx* c, int nb) {
       launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
       prof_next(c, 5);
       launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
-                                  (T*)c->tau + (int64_t)2 * p0 * g.nr, s);
+                                  (T*)c->tau + (int64_t)2 * p0 * g.nr, s, il);
     }
   }
   // 6. R

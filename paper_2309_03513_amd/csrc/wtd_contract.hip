@@ -513,31 +513,41 @@ __device__ __forceinline__ void rr_tile(int r, int slot, int& I, int& J) {
 
 // Per-thread constants of the tau staging: thread t stages point p = t % 8 and
 // combos c = g + 64 it (g = t / 8): row v_loc = (g >> 4) + 4 it, column w_loc = g & 15.
+// tau is in the kTauIl-interleaved layout: pair P at point r is element
+// ((P / kTauIl) N_r + r) kTauIl + P % kTauIl, so the 8 points of one staging
+// load read kTauIl consecutive pairs as one contiguous run.
 struct RRLoad {
-  int64_t col;        // w_loc N_r + r: column offset of the off-diagonal tiles
-  int64_t dcol[4];    // max(v_loc, w_loc) N_r + r: diagonal tiles
+  int64_t nrs;        // kTauIl N_r
+  int64_t rps;        // kTauIl r of this thread's point
+  int wl;             // w_loc
   int vrow[4];        // v_loc
   int drow[4];        // min(v_loc, w_loc)
+  int dcol[4];        // max(v_loc, w_loc)
 };
 
+__device__ __forceinline__ float rr_elem(const float* __restrict__ tau, const RRLoad& L, int P) {
+  return tau[(int64_t)(P >> kTauIlShift) * L.nrs + L.rps + (P & (kTauIl - 1))];
+}
+
+// Issue the global loads of round r's tau tiles (4 tiles, or 8 on the diagonal);
+// rowb[v] is the pair index of (v, v) minus v
 __device__ __forceinline__ void rr_fetch(float (&v)[8][RRTile::PER], const float* __restrict__ tau,
-                                         const int64_t* rbnr, const RRLoad& L, int r, int64_t nr) {
+                                         const int* rowb, const RRLoad& L, int r) {
   if (r < 7) {
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       int I, J;
       rr_tile(r, sl, I, J);
-      const float* base = tau + (int64_t)J * 16 * nr + L.col;
 #pragma unroll
-      for (int it = 0; it < RRTile::PER; ++it) v[sl][it] = base[rbnr[I * 16 + L.vrow[it]]];
+      for (int it = 0; it < RRTile::PER; ++it)
+        v[sl][it] = rr_elem(tau, L, rowb[I * 16 + L.vrow[it]] + J * 16 + L.wl);
     }
   } else {
 #pragma unroll
     for (int sl = 0; sl < 8; ++sl) {
-      const float* base = tau + (int64_t)sl * 16 * nr;
 #pragma unroll
       for (int it = 0; it < RRTile::PER; ++it)
-        v[sl][it] = base[rbnr[sl * 16 + L.drow[it]] + L.dcol[it]];
+        v[sl][it] = rr_elem(tau, L, rowb[sl * 16 + L.drow[it]] + sl * 16 + L.dcol[it]);
     }
   }
 }
@@ -565,7 +575,7 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
   typedef Mfma<float>::acc_t acc_t;
   __shared__ float s_a[8 * C::NE];   // trial tiles a~[b0 + b][16 K + v'], K = 0..7
   __shared__ float s_t[8 * C::NE];   // tau tiles of one round; reused to stage R
-  __shared__ int64_t s_rbnr[128];    // pair (v, w >= v) starts at s_rbnr[v] + w N_r
+  __shared__ int s_rowb[128];        // pair (v, w >= v) has index s_rowb[v] + w
   const int per = (ntile + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntile) return;
@@ -576,8 +586,7 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
   const int p_ld = threadIdx.x % C::TP;
   const int g_ld = threadIdx.x / C::TP;
   const int64_t rp = r0 + p_ld;
-  for (int v = threadIdx.x; v < 128; v += blockDim.x)
-    s_rbnr[v] = ((int64_t)v * nocc - (int64_t)v * (v + 1) / 2) * nr;
+  for (int v = threadIdx.x; v < 128; v += blockDim.x) s_rowb[v] = v * nocc - v * (v + 1) / 2;
 
   acc_t acc[C::TP];
 #pragma unroll
@@ -605,13 +614,15 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
     RRLoad L;
     {
       const int wl = g_ld & 15;
-      L.col = (int64_t)wl * nr + rp;
+      L.nrs = nr * kTauIl;
+      L.rps = rp * kTauIl;
+      L.wl = wl;
 #pragma unroll
       for (int it = 0; it < C::PER; ++it) {
         const int vl = (g_ld >> 4) + 4 * it;
         L.vrow[it] = vl;
         L.drow[it] = min(vl, wl);
-        L.dcol[it] = (int64_t)max(vl, wl) * nr + rp;
+        L.dcol[it] = max(vl, wl);
       }
     }
     // tau tiles of three rounds in flight (the memory latency under load spans
@@ -626,9 +637,9 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
           const int c = g_ld + it * (C::THREADS / C::TP);
           ta[K][it] = at[((int64_t)(b0 + (c & 15)) * nocc + K * 16 + (c >> 4)) * nr + rp];
         }
-      __syncthreads();  // s_rbnr
+      __syncthreads();  // s_rowb
 #pragma unroll
-      for (int r = 0; r < 3; ++r) rr_fetch(vb[r], tau, s_rbnr, L, r, nr);
+      for (int r = 0; r < 3; ++r) rr_fetch(vb[r], tau, s_rowb, L, r);
 #pragma unroll
       for (int K = 0; K < 8; ++K)
 #pragma unroll
@@ -649,7 +660,7 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
       __syncthreads();
       rr_put(s_t, vb[r % 3], r);
       __syncthreads();
-      if (r + 3 < 8) rr_fetch(vb[r % 3], tau, s_rbnr, L, r + 3, nr);
+      if (r + 3 < 8) rr_fetch(vb[r % 3], tau, s_rowb, L, r + 3);
       if (r == 5) load_response();
       int partner, slot;
       if (r < 7) {
@@ -861,13 +872,18 @@ __global__ void k_response_rows(int nb, int nocc, int64_t nr, const T* __restric
 }  // namespace
 
 template <typename T>
+bool contract_rr_applies(const Geometry& g, int nb, int nocc) {
+  return sizeof(T) == 4 && nocc == 128 && nb % 16 == 0 && g.nr % RRTile::TP == 0;
+}
+
+template <typename T>
 bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
                           const T* tau, const T* vh, const T* drho, const T* fxc, T ck, T alpha,
                           bool k1e, bool k1d, T* R, hipStream_t s) {
   const int nt = (nocc + 15) / 16;
   if (nt > 8) return false;
   if constexpr (sizeof(T) == 4) {
-    if (nocc == 128 && nb % 16 == 0 && g.nr % RRTile::TP == 0) {
+    if (contract_rr_applies<T>(g, nb, nocc)) {
       const int64_t nt64 = g.nr / RRTile::TP;
       WTD_REQUIRE(nt64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
       const int ntile = (int)nt64;
@@ -915,6 +931,8 @@ bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, con
   return true;
 }
 
+template bool contract_rr_applies<float>(const Geometry&, int, int);
+template bool contract_rr_applies<double>(const Geometry&, int, int);
 template bool launch_contract_mfma<float>(const Geometry&, int, int, const float*, const float*,
                                           const float*, const float*, const float*, const float*,
                                           float, float, bool, bool, float*, hipStream_t);

@@ -76,9 +76,16 @@ void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads,
                              int limit, cplx<T>* dst, hipStream_t s);
 template <typename T>
 void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s);
+// Pair potentials read by the round-robin contraction are stored interleaved by
+// groups of kTauIl pairs: pair P at point r is element ((P / kTauIl) N_r + r) kTauIl + P % kTauIl.
+constexpr int kTauIl = 4;
+constexpr int kTauIlShift = 2;
+static_assert((1 << kTauIlShift) == kTauIl, "interleave factor is a power of two");
+
+// il: write fields into the interleaved layout above
 template <typename T>
 void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, int nfield,
-                              T* out, hipStream_t s);
+                              T* out, hipStream_t s, bool il = false);
 template <typename T>
 void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int per_trial,
                               int nfield_per_trial, cplx<T>* wst, hipStream_t s);
@@ -93,6 +100,10 @@ void launch_contract(const Geometry& g, int nb, int nocc, const T* phi, const T*
                      const T* fxc, T ck, T alpha, bool k1e, bool k1d, T* R, hipStream_t s);
 
 // MFMA contraction for Nocc <= 128 (wtd_contract.hip); returns false if not applicable.
+// tau is [pair][N_r] (pairs v <= v' row-major), or, when contract_rr_applies(),
+// the same pairs in the kTauIl-interleaved layout.
+template <typename T>
+bool contract_rr_applies(const Geometry& g, int nb, int nocc);
 template <typename T>
 bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
                           const T* tau, const T* vh, const T* drho, const T* fxc, T ck, T alpha,

@@ -489,10 +489,15 @@ k_dstick_poisson(cplx<T>* __restrict__ dst, int n0, int nd, int nds, const T* __
 }
 
 // ---------------------------------------------------------------- density sticks -> real fields
+// Items (plane i0, pack) in XCD-contiguous ranges, pack fastest.  The two real
+// fields of pack p (fields 2p and 2p + 1) are written as planes of [field][N_r],
+// or, with il, into the layout that interleaves groups of kTauIl fields point
+// by point: field f at ((f / kTauIl) N_r + r) kTauIl + f % kTauIl (the packs of
+// one group are neighbouring items, so their partial lines meet in one L2).
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
-k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1, int n2, int nd,
-                    int nds,
+k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfield, int n0,
+                    int n1, int n2, int nd, int nds,
                     const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
                     const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
                     T* __restrict__ out) {
@@ -500,9 +505,11 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* twl = pl + plane;
+  const int item = xcd_item(n0 * npack);
+  if (item < 0) return;
   stage_twiddles<SN>(twl, tw1);
-  const int i0 = blockIdx.x;
-  const int pack = blockIdx.y;
+  const int i0 = item / npack;
+  const int pack = item - i0 * npack;
   const int64_t nr = (int64_t)n0 * plane;
   for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
   __syncthreads();
@@ -510,13 +517,26 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int nfield, int n0, int n1,
   for (int s = threadIdx.x; s < nd; s += blockDim.x) pl[k12[s]] = src[s];
   __syncthreads();
   plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  T* o1 = out + (int64_t)(2 * pack) * nr + (int64_t)i0 * plane;
-  T* o2 = o1 + nr;
   const bool has2 = 2 * pack + 1 < nfield;
-  for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-    const cplx<T> z = pl[i];
-    o1[i] = z.x;
-    if (has2) o2[i] = z.y;
+  if (il) {
+    const int f = 2 * pack;
+    T* o = out + (((int64_t)(f >> kTauIlShift) * nr + (int64_t)i0 * plane) << kTauIlShift) +
+           (f & (kTauIl - 1));
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      const cplx<T> z = pl[i];
+      if (has2)
+        *reinterpret_cast<cplx<T>*>(o + ((int64_t)i << kTauIlShift)) = z;
+      else
+        o[(int64_t)i << kTauIlShift] = z.x;
+    }
+  } else {
+    T* o1 = out + (int64_t)(2 * pack) * nr + (int64_t)i0 * plane;
+    T* o2 = o1 + nr;
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+      const cplx<T> z = pl[i];
+      o1[i] = z.x;
+      if (has2) o2[i] = z.y;
+    }
   }
 }
 
@@ -916,12 +936,12 @@ void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream
 
 template <typename T>
 void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, int nfield,
-                              T* out, hipStream_t s) {
-  dim3 grid(g.n0, npack);
+                              T* out, hipStream_t s, bool il) {
+  dim3 grid((unsigned)((g.n0 * npack + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
-  WTD_PLANE_LAUNCH(k_dsticks_to_fields, T, grid, lds, s, dst, nfield, g.n0, g.n1, g.n2, g.nd,
-                   g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
-                   static_cast<const cplx<T>*>(g.tw2), out);
+  WTD_PLANE_LAUNCH(k_dsticks_to_fields, T, grid, lds, s, dst, npack, il ? 1 : 0, nfield, g.n0,
+                   g.n1, g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2,
+                   static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2), out);
 }
 
 template <typename T>
@@ -1009,7 +1029,7 @@ void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_fl
                                            cplx<T>*, hipStream_t);                             \
   template void launch_dstick_poisson<T>(const Geometry&, cplx<T>*, int, hipStream_t);         \
   template void launch_dsticks_to_fields<T>(const Geometry&, const cplx<T>*, int, int, T*,     \
-                                            hipStream_t);                                      \
+                                            hipStream_t, bool);                                \
   template void launch_fields_to_wsticks<T>(const Geometry&, const T*, int, int, int,          \
                                             cplx<T>*, hipStream_t);                            \
   template void launch_wsticks_to_sphere<T>(const Geometry&, cplx<T>*, int, hipStream_t);      \
