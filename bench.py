@@ -28,15 +28,48 @@ MEV = 3.674932e-5  # Hartree per meV
 METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at ΔE≤1 meV"
 
 
-# HBM bytes per launch of the dominant kernel measured with rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (scaled by a plain-copy calibration), valid only for the kernel
-# sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
+# HBM bytes per launch (average over a stage's launches in one apply) measured with
+# rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain-copy calibration; valid only
+# for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
+    "pair_plane_fwd": {
+        "bytes": 843.4e6,
+        "sources": {
+            "paper_2309_03513_amd/csrc/wtd_transforms.hip":
+                "ebae947baffb38e3ec2490041cd98151f40651b2f255ac63125b938c4b171613",
+            "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
+                "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
+            "paper_2309_03513_amd/csrc/wtd_fft.h":
+                "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+        },
+    },
+    "pair_stick_poisson": {
+        "bytes": 1299.8e6,
+        "sources": {
+            "paper_2309_03513_amd/csrc/wtd_transforms.hip":
+                "ebae947baffb38e3ec2490041cd98151f40651b2f255ac63125b938c4b171613",
+            "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
+                "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
+            "paper_2309_03513_amd/csrc/wtd_fft.h":
+                "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+        },
+    },
+    "pair_plane_inv": {
+        "bytes": 1988.6e6,
+        "sources": {
+            "paper_2309_03513_amd/csrc/wtd_transforms.hip":
+                "ebae947baffb38e3ec2490041cd98151f40651b2f255ac63125b938c4b171613",
+            "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
+                "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
+            "paper_2309_03513_amd/csrc/wtd_fft.h":
+                "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+        },
+    },
     "contract": {
-        "bytes": 19360.5e6,
+        "bytes": 19662.4e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "224d84ab3811daa4babf8e90c47699d2d173cc8fe8b5eb10648e6ce3c427f7bc",
+                "044d7cb51965de0b2a32862e2eab3898fc5ad437aacf8fbf81b7f3ecb53eb34a",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
         },
