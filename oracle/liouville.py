@@ -1,4 +1,5 @@
-"""The Tamm-Dancoff Liouville operator L = D + K1e - K1d applied to trial sets (oracle).
+"""The Tamm-Dancoff Liouville operator L = D + K1e - K1d applied to trial sets (oracle),
+and the full operator D + K1e - K1d + K2e - K2d of the Z-vector equation.
 
 Follows Sec. 2.1 of the paper: the D term (Eq. dterm), the density-response
 term K1e with f_Hxc = v_c + f_xc (Eq. k1eterm), the exact-exchange term K1d
@@ -25,6 +26,12 @@ Readings of the paper taken here (the paper is silent or general on these):
 * The operator is defined on the FFT grid: products are formed at grid points
   and integrals are grid quadratures.
 
+* K2e and K2d (Eqs. k2eterm, k2dterm) enter the Z-vector equation (Eq.
+  z-v-eq) and the off-diagonal blocks of Eq. TDDFT_VEE.  K2e's density is
+  sum_v' conj(a_v') phi_v', K2d's pairs are conj(a_v') phi_v, Poisson-solved
+  and multiplied by phi_v'.  At the Gamma point every field here is real, so
+  K2e equals K1e; the conjugates are kept to follow the equations.
+
 Steps, for every trial b and occupied v (Hartree units):
  1. S_cv = <phi_c|a_v>, a~_v = sum_c phi_c S_cv
  2. phi_v(r_j), a~_v(r_j) on the grid
@@ -32,6 +39,8 @@ Steps, for every trial b and occupied v (Hartree units):
  4. V(r_j) = c_K [ (v_c * drho)(r_j) + f_xc(r_j) drho(r_j) ]
  5. tau_vv'(r_j) = (v_c * (phi_v phi_v'))(r_j)
  6. R_v(r_j) = phi_v(r_j) V(r_j) - alpha sum_v' tau_vv'(r_j) a~_v'(r_j)
+    (full operator: V also carries K2e's density, and R_v also gets
+    - alpha sum_v' phi_v'(r_j) (v_c * (conj(a~_v') phi_v))(r_j), the K2d term)
  7. la_v = sum_c phi_c [ (eps_c - eps_v) S_cv + (Omega/N_r) sum_j phi_c(r_j) R_v(r_j) ]
 """
 from __future__ import annotations
@@ -43,7 +52,10 @@ from .planewave import coefficients, coulomb_kernel, gamma_inner, poisson, real_
 TERM_D = 1
 TERM_K1E = 2
 TERM_K1D = 4
-TERM_ALL = 7
+TERM_ALL = 7      # the TDA operator D + K1e - K1d
+TERM_K2E = 8
+TERM_K2D = 16
+TERM_FULL = 31    # D + K1e - K1d + K2e - K2d (Eq. z-v-eq)
 
 
 def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None, progress=None):
@@ -84,9 +96,13 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None,
 
     # steps 3-4: density response and its Hartree + f_xc potential
     V = None
-    if terms & TERM_K1E and s.c_k != 0.0:
+    if terms & (TERM_K1E | TERM_K2E) and s.c_k != 0.0:
         kern = coulomb_kernel(cell, n, s.v_g0)
-        drho = np.stack([np.einsum("vxyz,vxyz->xyz", phi, at[b]) for b in range(nb)])
+        drho = np.zeros((nb,) + n)
+        if terms & TERM_K1E:       # sum_v' conj(phi_v') a_v'
+            drho += np.stack([np.einsum("vxyz,vxyz->xyz", np.conj(phi), at[b]) for b in range(nb)])
+        if terms & TERM_K2E:       # sum_v' conj(a_v') phi_v'
+            drho += np.stack([np.einsum("vxyz,vxyz->xyz", np.conj(at[b]), phi) for b in range(nb)])
         V = s.c_k * (poisson(drho, kern) + s.fxc[None] * drho)
         say("oracle: density response potential")
 
@@ -102,6 +118,13 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None,
             for b in range(nb):
                 R[b, i] -= s.alpha * np.einsum("uxyz,uxyz->xyz", tau, at[b])
             say(f"oracle: exchange for row {v}")
+    if terms & TERM_K2D and s.alpha != 0.0:
+        kern = coulomb_kernel(cell, n, s.v_g0)
+        for i, v in enumerate(rows):
+            for b in range(nb):
+                w = poisson(np.conj(at[b]) * phi[v][None], kern)          # [v'][n]
+                R[b, i] -= s.alpha * np.einsum("uxyz,uxyz->xyz", phi, w)
+            say(f"oracle: K2d for row {v}")
 
     # step 7: back to the projected plane-wave space
     if projector == "span":

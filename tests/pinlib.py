@@ -157,3 +157,42 @@ def casida_matrix(s, with_fxc=True):
                                                   omega, s.v_g0)
             A[i, j] = val
     return A
+
+
+def casida_b_matrix(s, with_fxc=True):
+    """Off-diagonal block of Eq. TDDFT_VEE for real (Gamma-point) orbitals:
+    B[(v,c),(v',c')] = c_K[(cv|v'c') + (cv|f_xc|v'c')] - alpha (cv'|c'v), the
+    matrix of K2e - K2d in the transition basis, from direct sums."""
+    cell = np.asarray(s.cell, dtype=np.float64)
+    omega = float(np.prod(cell))
+    nocc, nc = s.c_occ.shape[0], s.c_cond.shape[0]
+    rcv = {}
+    for v in range(nocc):
+        for c in range(nc):
+            rcv[v, c], mmax = pair_density_g(s.c_cond[c], s.c_occ[v], s.mill, omega)
+    fx = None
+    if with_fxc:
+        po = direct_real_space(s.c_occ, s.mill, cell, s.n).reshape(nocc, -1)
+        pc = direct_real_space(s.c_cond, s.mill, cell, s.n).reshape(nc, -1)
+        prod = (pc[None, :, :] * po[:, None, :]).reshape(nocc * nc, -1)
+        nr = prod.shape[1]
+        fx = (omega / nr) * (prod * s.fxc.reshape(1, -1)) @ prod.T
+    dim = nocc * nc
+    B = np.zeros((dim, dim))
+    for i in range(dim):
+        v, c = divmod(i, nc)
+        for j in range(dim):
+            v2, c2 = divmod(j, nc)
+            val = 0.0
+            if s.c_k != 0.0:
+                # (cv|v'c'): pair densities phi_c phi_v and phi_v' phi_c' (real orbitals)
+                val += s.c_k * coulomb_integral(rcv[v, c], rcv[v2, c2], mmax, cell, omega,
+                                                s.v_g0)
+                if fx is not None:
+                    val += s.c_k * fx[i, j]
+            if s.alpha != 0.0:
+                # (cv'|c'v): pair densities phi_c phi_v' and phi_c' phi_v
+                val -= s.alpha * coulomb_integral(rcv[v2, c], rcv[v, c2], mmax, cell, omega,
+                                                  s.v_g0)
+            B[i, j] = val
+    return B
