@@ -96,6 +96,32 @@ wtd_status wtd_destroy(wtd_ctx *ctx);
  * re-transform them to real space.  Asynchronous on the context stream.        */
 wtd_status wtd_set_occ(wtd_ctx *ctx, const double *c_occ);
 
+/* Keep the pair potentials tau_vv' = v_c * (phi_v phi_v') (Eq. trunc) from one
+ * apply to the next.  They depend on the occupied orbitals only, so every apply
+ * of a Davidson run (Sec. 4) can reuse them; wtd_set_occ and the orbital
+ * gradient of wtd_apply_liouville_bwd invalidate them, and the next apply
+ * recomputes them.  Off by default (every apply recomputes the pairs).
+ * on: 1 keep, 0 recompute every apply.  Host-side flag, ordered with the
+ * context stream like every other call.
+ * Errors: WTD_ERR_ARG (null), WTD_ERR_SHAPE (on = 1 where the exchange runs
+ * row-blocked: Nocc > 128 or a forced row block, whose pair potentials are
+ * formed one block pair at a time and do not fit at once).                      */
+wtd_status wtd_cache_pairs(wtd_ctx *ctx, int32_t on);
+
+/* Autotuner for the launch shape of the apply (Sec. 4's FFT batching):
+ * times whole applies of an nb-trial block for every candidate and keeps the
+ * fastest by median of reps timed applies, first the number of workgroups the
+ * density reduction of each trial is split over (8, 4, 2, 1), then the number
+ * of packed pairs per Poisson batch (the batch allocated at creation, 512 or
+ * fewer, and its halvings down to 16, in whole groups of 4 packs).
+ * Synchronous; allocates and frees two blocks of nb trial vectors.  The pair
+ * potentials do not depend on the batch; the density split changes the
+ * summation order of the density response (rounding only).
+ * chunk, groups: the chosen values (either may be NULL).
+ * Errors: WTD_ERR_ARG (null context, reps outside [1, 100]), WTD_ERR_SHAPE
+ * (nb outside [1, max_nb]), WTD_ERR_OOM.                                        */
+wtd_status wtd_autotune(wtd_ctx *ctx, int32_t nb, int32_t reps, int32_t *chunk, int32_t *groups);
+
 /* la = P L P a for a block of nb trial sets (Eq. TDDFT_VEXX_TDA's left-hand
  * side, the paper's Sec. 2.1 terms selected by term_mask).
  * a, la: device [nb][nocc][npw][2] in the context precision (double or float);
@@ -124,7 +150,9 @@ wtd_status wtd_apply_liouville_bwd(wtd_ctx *ctx, int32_t nb, const void *a, cons
                                    void *g_a, void *g_occ);
 
 /* Block Davidson for the nroots lowest eigenpairs of L (Sec. 4; normalisation
- * sum_v <x_v|x_v> = 1 of Eq. ltda).  Synchronous.
+ * sum_v <x_v|x_v> = 1 of Eq. ltda).  Synchronous.  Where the exchange is not
+ * row-blocked the pair potentials are formed once per call and reused by every
+ * apply of the run (as with wtd_cache_pairs).
  * nb: block size (nroots <= nb <= max_nb); tol: residual 2-norm per root;
  * max_sub: basis cap before restart (<= 0: 4*nb); guess: device
  * [nb][nocc][npw][2] FP64 or NULL (lowest unit transitions).

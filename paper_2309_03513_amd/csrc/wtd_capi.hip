@@ -79,8 +79,12 @@ struct wtd_ctx {
   void* R = nullptr;         // [max_nb][nocc][nr]
   void* drho = nullptr;      // [max_nb][nr]
   void* vh = nullptr;        // [max_nb][nr]
-  void* drho_part = nullptr; // [kDrhoGroups][max_nb][nr] partial densities
+  void* drho_part = nullptr; // [8][max_nb][nr] partial densities
   void* tau = nullptr;       // [npairs][nr]
+  // Pair potentials depend on the occupied orbitals only: with tau_cache on they
+  // are kept from one apply to the next until the orbitals change.
+  bool tau_cache = false;
+  bool tau_valid = false;
   void* wst = nullptr;       // [max packs][n0][nw] complex
   void* dst = nullptr;       // [pair chunk][n0][nd] complex
   void* ag = nullptr;        // [max_nb][nocc][2 npw]
@@ -91,6 +95,8 @@ struct wtd_ctx {
   void* gemm_scratch = nullptr;  // split-K partial products
   size_t gemm_scratch_elems = 0;
   int npairs = 0, npack_pairs = 0, pair_chunk = 0;
+  int max_pair_chunk = 0;    // packs the density-stick buffer holds
+  int drho_groups = 8;       // workgroups per trial of the density reduction
   int4* quads = nullptr;     // pair packs
   int4* hquads = nullptr;    // Hartree packs
   // backward-only buffers, allocated on the first backward call
@@ -514,6 +520,7 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   if (c->pair_chunk >= 4) c->pair_chunk = c->pair_chunk / 4 * 4;
   if (c->row_block)
     c->pair_chunk = std::min(c->pair_chunk, (int)((tau_fields + 1) / 2));
+  c->max_pair_chunk = c->pair_chunk;
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
   c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nds * sizeof(cplx<T>));
   c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
@@ -552,7 +559,7 @@ void apply_core(wtd_ctx* c, int nb) {
   const bool k1d = (c->mask & WTD_TERM_K1D) && c->alpha != 0.0;
   const int F = nb * nocc;
   if (!k1e && !k1d) {
-    WTD_HIP(hipMemsetAsync(c->Q, 0, (size_t)F * nc * sizeof(T), s));
+    launch_zero<T>((T*)c->Q, (int64_t)F * nc, s);
     return;
   }
   const int npt = (nocc + 1) / 2;
@@ -561,7 +568,7 @@ void apply_core(wtd_ctx* c, int nb) {
   launch_sphere_to_wsticks<T>(g, (const T*)c->ag, F, npw, nb, nocc, (cplx<T>*)c->wst, s);
   launch_wsticks_to_fields<T>(g, (const cplx<T>*)c->wst, nb, nocc, nocc,
                               (T)(1.0 / std::sqrt(g.omega)), (T*)c->at, (const T*)c->phi,
-                              k1e ? (T*)c->drho : nullptr, s, (T*)c->drho_part, kDrhoGroups);
+                              k1e ? (T*)c->drho : nullptr, s, (T*)c->drho_part, c->drho_groups);
   // 4. Hartree potential of drho_b
   if (k1e) {
     prof_next(c, 2);
@@ -599,7 +606,7 @@ void apply_core(wtd_ctx* c, int nb) {
   // of kTauIl pairs when the round-robin contraction reads them (a chunk starts
   // on a whole group, so its groups start at field 2 p0 in either layout)
   const bool il = contract_rr_applies<T>(g, nb, nocc);
-  if (k1d && !c->row_block) {
+  if (k1d && !c->row_block && !(c->tau_cache && c->tau_valid)) {
     WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
                 WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
     for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
@@ -614,6 +621,7 @@ void apply_core(wtd_ctx* c, int nb) {
       launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
                                   (T*)c->tau + (int64_t)2 * p0 * g.nr, s, il);
     }
+    c->tau_valid = c->tau_cache;
   }
   // 6. R
   prof_next(c, 6);
@@ -726,7 +734,7 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
   const bool k1e = (c->mask & WTD_TERM_K1E) && c->ck != 0.0;
   const bool k1d = (c->mask & WTD_TERM_K1D) && c->alpha != 0.0;
   if (!k1e && !k1d) {
-    WTD_HIP(hipMemsetAsync(g_occ, 0, (size_t)nocc * K * sizeof(T), s));
+    launch_zero<T>(g_occ, (int64_t)nocc * K, s);
     return;
   }
   const T iso = (T)(1.0 / std::sqrt(G.omega));
@@ -745,6 +753,8 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
   launch_wsticks_to_fields<T>(G, (const cplx<T>*)c->wst, nb, nocc, nocc, iso, (T*)c->gt,
                               (const T*)c->phi, k1e ? (T*)c->drhog : nullptr, s);
   // exchange part: P_wv' = M_wv' + M_v'w -> v_c * P -> gamma = -alpha sum_v' phi_v' (v_c * P)
+  // (the pair-density fields overwrite the pair potentials)
+  if (k1d) c->tau_valid = false;
   if (k1d && c->row_block) {
     // gamma = -alpha sum_v' phi_v' v_c * P_wv', block pair by block pair
     launch_response_rows<T>(G, 1, nocc, (const T*)c->phi, nullptr, nullptr, nullptr, (T)0, false,
@@ -785,7 +795,7 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
                          c->pidx, nullptr, nullptr, (const T*)c->fxc, (T)0, (T)c->alpha, false,
                          true, (T*)c->gamma, s);
   } else {
-    WTD_HIP(hipMemsetAsync(c->gamma, 0, (size_t)nocc * G.nr * sizeof(T), s));
+    launch_zero<T>((T*)c->gamma, (int64_t)nocc * G.nr, s);
   }
   // response part
   if (k1e) {
@@ -802,6 +812,86 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
   launch_extract_sphere<T>(G, (const cplx<T>*)c->wst, 1, nocc, nocc, npw,
                            (T)(std::sqrt(G.omega) / (double)G.nr), g_occ, s);
   launch_weights<T>(g_occ, nocc, npw, 1, s);
+}
+
+// ---------------------------------------------------------------- autotuner
+// Times whole applies of an nb-trial block (zero input: the transforms and the
+// contraction do the same work for any values) for each candidate setting and
+// keeps the fastest by median of reps timed applies.
+template <typename T>
+void autotune_impl(wtd_ctx* c, int nb, int reps, int32_t* chunk_out, int32_t* groups_out) {
+  hipStream_t s = c->stream;
+  const size_t n = (size_t)nb * c->nocc * 2 * c->npw;
+  struct Tmp {
+    void* a = nullptr;
+    void* la = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Tmp() {
+      if (a) (void)hipFree(a);
+      if (la) (void)hipFree(la);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } t;
+  if (hipMalloc(&t.a, n * sizeof(T)) != hipSuccess || hipMalloc(&t.la, n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw StatusError{WTD_ERR_OOM, "autotuner trial block allocation failed"};
+  }
+  WTD_HIP(hipEventCreate(&t.e0));
+  WTD_HIP(hipEventCreate(&t.e1));
+  launch_zero<T>((T*)t.a, (int64_t)n, s);
+  const bool prof_on = c->prof.on, cache_on = c->tau_cache;
+  c->prof.on = false;
+  c->tau_cache = false;
+  auto time_apply = [&]() {
+    apply_impl<T>(c, nb, (const T*)t.a, (T*)t.la);  // warm-up
+    std::vector<float> ms(reps);
+    for (int r = 0; r < reps; ++r) {
+      WTD_HIP(hipEventRecord(t.e0, s));
+      apply_impl<T>(c, nb, (const T*)t.a, (T*)t.la);
+      WTD_HIP(hipEventRecord(t.e1, s));
+      WTD_HIP(hipEventSynchronize(t.e1));
+      WTD_HIP(hipEventElapsedTime(&ms[r], t.e0, t.e1));
+    }
+    std::sort(ms.begin(), ms.end());
+    return ms[reps / 2];
+  };
+  try {
+    // density split of the trial transform
+    float best = 0.f;
+    int best_g = c->drho_groups;
+    for (int gs : {8, 4, 2, 1}) {
+      c->drho_groups = gs;
+      const float m = time_apply();
+      if (gs == 8 || m < best) best = m, best_g = gs;
+    }
+    c->drho_groups = best_g;
+    // packed pairs per Poisson batch: halvings of the allocated batch, whole
+    // groups of 4 packs
+    int best_c = c->pair_chunk;
+    if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D)) {
+      best = 0.f;
+      bool first = true;
+      for (int ch = c->max_pair_chunk; ch >= 16; ch /= 2) {
+        const int cand = ch == c->max_pair_chunk ? ch : ch / 4 * 4;
+        c->pair_chunk = cand;
+        const float m = time_apply();
+        if (first || m < best) best = m, best_c = cand;
+        first = false;
+      }
+    }
+    c->pair_chunk = best_c;
+  } catch (...) {
+    c->prof.on = prof_on;
+    c->tau_cache = cache_on;
+    c->tau_valid = false;
+    throw;
+  }
+  c->prof.on = prof_on;
+  c->tau_cache = cache_on;
+  c->tau_valid = false;
+  if (chunk_out) *chunk_out = c->pair_chunk;
+  if (groups_out) *groups_out = c->drho_groups;
 }
 
 // ---------------------------------------------------------------- Davidson (FP64)
@@ -834,6 +924,16 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
   max_sub = (int)std::min<int64_t>(max_sub, n);
   WTD_REQUIRE(max_sub <= 256, WTD_ERR_SHAPE, "max_sub must not exceed 256");
   DavWork w{c, {}};
+  // every apply of the run sees the same orbitals: form the pair potentials once
+  struct KeepPairs {
+    wtd_ctx* c;
+    bool saved;
+    ~KeepPairs() {
+      c->tau_cache = saved;
+      if (!saved) c->tau_valid = false;
+    }
+  } keep{c, c->tau_cache};
+  if (!c->row_block) c->tau_cache = true;
   double* V = w.alloc((size_t)max_sub * n);
   double* W = w.alloc((size_t)max_sub * n);
   double* H = w.alloc((size_t)max_sub * max_sub);
@@ -1054,10 +1154,36 @@ wtd_status wtd_destroy(wtd_ctx* ctx) {
 wtd_status wtd_set_occ(wtd_ctx* ctx, const double* c_occ) {
   return guarded([&]() -> wtd_status {
     WTD_REQUIRE(ctx && c_occ, WTD_ERR_ARG, "null argument");
+    ctx->tau_valid = false;
     if (ctx->prec == WTD_FP64)
       transform_occ<double>(ctx, c_occ);
     else
       transform_occ<float>(ctx, c_occ);
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_cache_pairs(wtd_ctx* ctx, int32_t on) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    WTD_REQUIRE(!on || ctx->row_block == 0, WTD_ERR_SHAPE,
+                "the row-blocked exchange keeps the pair potentials of one block pair only");
+    ctx->tau_cache = on != 0;
+    ctx->tau_valid = false;
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_autotune(wtd_ctx* ctx, int32_t nb, int32_t reps, int32_t* chunk,
+                        int32_t* groups) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
+    WTD_REQUIRE(reps >= 1 && reps <= 100, WTD_ERR_ARG, "reps out of range [1, 100]");
+    if (ctx->prec == WTD_FP64)
+      autotune_impl<double>(ctx, nb, reps, chunk, groups);
+    else
+      autotune_impl<float>(ctx, nb, reps, chunk, groups);
     return WTD_OK;
   });
 }

@@ -147,6 +147,8 @@ void launch_dterm_combine(int nb, int nocc, int nc, const T* S, const T* Q, cons
                           const double* eps_cond, bool with_d, T* out, hipStream_t s);
 template <typename Tin, typename Tout>
 void launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s);
+template <typename T>
+void launch_zero(T* p, int64_t n, hipStream_t s);
 void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_float,
                            const double* X, const double* eps_occ, const double* eps_cond,
                            bool with_d, double* T, hipStream_t s);

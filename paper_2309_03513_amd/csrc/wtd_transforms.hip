@@ -781,6 +781,13 @@ __global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, in
   if (i < n) out[i] = (Tout)in[i];
 }
 
+// Clears n elements (a kernel rather than a memset node, so callers may capture it in a graph).
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = (T)0;
+}
+
 __global__ void k_transition_out(int nb, int nocc, int nc, const void* __restrict__ Q, int qf,
                                  const double* __restrict__ X, const double* __restrict__ eo,
                                  const double* __restrict__ ec, int with_d,
@@ -1010,6 +1017,17 @@ void launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s) {
                      in, out, n);
   WTD_HIP(hipGetLastError());
 }
+
+template <typename T>
+void launch_zero(T* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_zero<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  WTD_HIP(hipGetLastError());
+}
+
+template void launch_zero<float>(float*, int64_t, hipStream_t);
+template void launch_zero<double>(double*, int64_t, hipStream_t);
 
 void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_float,
                            const double* X, const double* eo, const double* ec, bool with_d,

@@ -25,7 +25,7 @@ FP64, FP32 = 0, 1
 TERM_D, TERM_K1E, TERM_K1D, TERM_ALL = 1, 2, 4, 7
 
 EXPORTS = ["wtd_debug_gemm", "wtd_create", "wtd_destroy", "wtd_set_occ", "wtd_apply_liouville",
-           "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson",
+           "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson", "wtd_cache_pairs", "wtd_autotune",
            "wtd_profile_enable", "wtd_profile_read", "wtd_workspace_bytes", "wtd_last_error"]
 
 
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.wtd_apply_transition.argtypes = [vp, i32, vp, vp]
     lib.wtd_apply_liouville_bwd.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.wtd_davidson.argtypes = [vp, i32, i32, f64, i32, i32, vp, vp, vp, vp, vp]
+    lib.wtd_cache_pairs.argtypes = [vp, i32]
+    lib.wtd_autotune.argtypes = [vp, i32, i32, vp, vp]
     lib.wtd_profile_enable.argtypes = [vp, i32]
     lib.wtd_profile_read.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.wtd_workspace_bytes.argtypes = [vp, vp]
@@ -240,6 +242,17 @@ class Liouville:
             _ptr(g), omega.ctypes.data_as(ctypes.c_void_p), _ptr(x),
             resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nit)))
         return omega, x, resid, nit.value, st
+
+    def cache_pairs(self, on=True):
+        """Keep the pair potentials between applies until the orbitals change."""
+        _check(self._lib.wtd_cache_pairs(self._handle(), 1 if on else 0))
+
+    def autotune(self, nb=None, reps=3):
+        """Pick the pair batch and density split by timing applies; returns (chunk, groups)."""
+        ch, gr = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.wtd_autotune(self._handle(), int(nb or self.max_nb), int(reps),
+                                      ctypes.byref(ch), ctypes.byref(gr)))
+        return ch.value, gr.value
 
     def profile(self, on=True):
         _check(self._lib.wtd_profile_enable(self._handle(), 1 if on else 0))
