@@ -58,7 +58,10 @@ typedef enum {
 
 typedef enum { WTD_FP64 = 0, WTD_FP32 = 1 } wtd_precision;
 
-enum { WTD_TERM_D = 1, WTD_TERM_K1E = 2, WTD_TERM_K1D = 4, WTD_TERM_ALL = 7 };
+enum { WTD_TERM_D = 1, WTD_TERM_K1E = 2, WTD_TERM_K1D = 4, WTD_TERM_ALL = 7,
+       /* the terms of the full operator of the Z-vector equation (Eq. z-v-eq),
+        * applied only by wtd_apply_full and wtd_solve_zvector                   */
+       WTD_TERM_K2E = 8, WTD_TERM_K2D = 16, WTD_TERM_FULL = 31 };
 
 typedef struct {
   int32_t n[3];            /* FFT grid; each n_i > 2 max|m_i| and n_i a product of 2,3,5   */
@@ -133,6 +136,35 @@ wtd_status wtd_apply_liouville(wtd_ctx *ctx, int32_t nb, const void *a, void *la
  * T = Phi_c^T L Phi_c X, X and T device [nb][nocc][ncond] FP64.  This is the
  * form the Davidson solver applies (Sec. 4).  Asynchronous.                     */
 wtd_status wtd_apply_transition(wtd_ctx *ctx, int32_t nb, const double *X, double *T);
+
+/* la = P (D + K1e - K1d + K2e - K2d) P a, the operator of the Z-vector
+ * equation (Eq. z-v-eq; the blocks of Eq. TDDFT_VEE summed), with the terms the
+ * context's term_mask selects (K2e needs WTD_TERM_K2E, K2d WTD_TERM_K2D; a
+ * context created with WTD_TERM_ALL applies the TDA operator here too).
+ * K2e: Eq. k2eterm, whose density sum_v' conj(a_v') phi_v' equals K1e's for
+ * the real Gamma-point fields.  K2d: Eq. k2dterm, the Poisson-solved products
+ * conj(a_v') phi_v of every (v', v), N_b N_occ^2 of them (about 32 times the
+ * pair work of K1d at N_b = 16), formed in the pair-potential buffer, so the
+ * pair cache of wtd_cache_pairs is dropped by every apply with K2d.
+ * Layout, ownership and errors as wtd_apply_liouville.  Asynchronous.           */
+wtd_status wtd_apply_full(wtd_ctx *ctx, int32_t nb, const void *a, void *la);
+
+/* Conjugate-gradient solve of the Z-vector equation (Eq. z-v-eq) with the
+ * inexact Krylov scheme of Sec. 3.3: the full operator (as wtd_apply_full) is
+ * applied until every unconverged residual norm is below lambda_thr, K2d is
+ * dropped from then on (lambda_thr = 0: never).  The nrhs right-hand sides are
+ * independent CG systems solved side by side, one block apply per iteration;
+ * CG runs in FP64 in transition coordinates (U projected on the conduction
+ * orbitals, Z = Phi_c X), the applies in the context precision.  Synchronous.
+ * U, Z: device [nrhs][nocc][npw][2] FP64, not aliased; tol: residual 2-norm per
+ * system (transition coordinates); resid host [nrhs] (may be NULL); n_iter:
+ * iterations; n_exact: iterations that applied the full operator (may be NULL).
+ * Returns WTD_NOT_CONVERGED (a warning, outputs valid) after max_iter.
+ * Errors: WTD_ERR_ARG, WTD_ERR_SHAPE (nrhs outside [1, max_nb]),
+ * WTD_ERR_NONFINITE (CG breakdown: the operator is not positive definite).    */
+wtd_status wtd_solve_zvector(wtd_ctx *ctx, int32_t nrhs, const double *U, double tol,
+                             int32_t max_iter, double lambda_thr, double *Z, double *resid,
+                             int32_t *n_iter, int32_t *n_exact);
 
 /* Gradients of E = sum Re(conj(g_la) la), la = L a, with respect to the
  * (re, im) parts of a and of the occupied coefficients c_occ (the derivative of

@@ -55,20 +55,35 @@ def cg_inexact(matvec_exact, matvec_approx, rhs, tol=1e-8, max_iter=200, lambda_
 def solve_zvector_transition(s, U, tol=1e-8, max_iter=200, lambda_thr=0.0):
     """Z-vectors for right-hand sides U [nrhs][nocc][nc] in transition coordinates.
 
-    Returns (Z [nrhs][nocc][nc], residual norms, iterations, exact applies)."""
+    The right-hand sides are solved side by side, one CG each, with one shared
+    operator per iteration: the approximate operator is taken from the first
+    iteration at which every unconverged residual norm is below lambda_thr (for
+    one right-hand side this is the rule of cg_inexact).  A converged system is
+    left as it is.  Returns (Z [nrhs][nocc][nc], residual norms, iterations,
+    applies of the exact operator)."""
     U = np.asarray(U, dtype=np.float64)
     nrhs, nocc, nc = U.shape
-
-    def mv(terms):
-        return lambda x: apply_transition(s, x.reshape(1, nocc, nc), terms=terms).ravel()
-
-    exact, approx = mv(TERM_FULL), mv(TERM_FULL & ~TERM_K2D)
-    Z = np.zeros_like(U)
-    res, its, nex = [], [], []
-    for k in range(nrhs):
-        z, rn, it, ne = cg_inexact(exact, approx, U[k], tol, max_iter, lambda_thr)
-        Z[k] = z.reshape(nocc, nc)
-        res.append(rn)
-        its.append(it)
-        nex.append(ne)
-    return Z, np.array(res), np.array(its), np.array(nex)
+    Z = np.zeros((nrhs, nocc * nc))
+    R = U.reshape(nrhs, -1).copy()
+    P = R.copy()
+    rr = np.sum(R * R, axis=1)
+    active = np.sqrt(rr) > tol
+    use_exact = True
+    n_exact = 0
+    it = 0
+    while active.any() and it < max_iter:
+        if use_exact and lambda_thr > 0.0 and np.all(np.sqrt(rr[active]) < lambda_thr):
+            use_exact = False
+        terms = TERM_FULL if use_exact else TERM_FULL & ~TERM_K2D
+        AP = apply_transition(s, P.reshape(nrhs, nocc, nc), terms=terms).reshape(nrhs, -1)
+        n_exact += int(use_exact)
+        for k in np.flatnonzero(active):
+            step = rr[k] / float(P[k] @ AP[k])
+            Z[k] += step * P[k]
+            R[k] -= step * AP[k]
+            rr_new = float(R[k] @ R[k])
+            P[k] = R[k] + (rr_new / rr[k]) * P[k]
+            rr[k] = rr_new
+        active = np.sqrt(rr) > tol
+        it += 1
+    return Z.reshape(nrhs, nocc, nc), np.sqrt(rr), it, n_exact

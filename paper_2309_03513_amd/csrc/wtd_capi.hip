@@ -39,11 +39,11 @@ struct DevBuf {
 
 struct Profiler {
   bool on = false;
-  static constexpr int kStages = 10;
+  static constexpr int kStages = 11;
   const char* names[kStages] = {"project_in",     "trial_to_grid", "hartree",
                                 "pair_plane_fwd", "pair_stick_poisson", "pair_plane_inv",
                                 "contract",       "grid_to_sphere", "project_out",
-                                "davidson_small"};
+                                "davidson_small", "k2d"};
   double ms[kStages] = {};
   int64_t calls[kStages] = {};
   std::vector<hipEvent_t> pool;
@@ -99,6 +99,11 @@ struct wtd_ctx {
   int drho_groups = 8;       // workgroups per trial of the density reduction
   int4* quads = nullptr;     // pair packs
   int4* hquads = nullptr;    // Hartree packs
+  // K2d packs: products a_bv' phi_v of trial b, pair q = v' nocc + v, two per pack;
+  // field indices count phi (nocc fields) then the trial fields (max_nb * nocc)
+  int4* k2quads = nullptr;   // [max_nb][k2_npk]
+  int k2_npk = 0;
+  size_t tau_fields = 0;     // fields the pair-potential buffer holds
   // backward-only buffers, allocated on the first backward call
   bool bwd_ready = false;
   void* gt = nullptr;        // [max_nb][nocc][nr] cotangent fields g~
@@ -498,8 +503,10 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   // workspace
   const int npt = (nocc + 1) / 2;
   const size_t nwp = (size_t)std::max(mnb * npt, npt);
-  c->phi = dalloc(c, (size_t)nocc * nr * sizeof(T));
-  c->at = dalloc(c, (size_t)mnb * nocc * nr * sizeof(T));
+  // phi and the projected trial fields share one allocation, so that pair
+  // kernels can form products of a trial field and an orbital (K2d)
+  c->phi = dalloc(c, ((size_t)nocc + (size_t)mnb * nocc) * nr * sizeof(T));
+  c->at = (T*)c->phi + (size_t)nocc * nr;
   c->R = dalloc(c, (size_t)mnb * nocc * nr * sizeof(T));
   c->drho = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
@@ -508,8 +515,26 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   const size_t tau_fields =
       c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs)
                    : ((size_t)c->npairs + 7) / 8 * 8;
-  if (c->alpha != 0.0 && (c->mask & WTD_TERM_K1D))
+  if (c->alpha != 0.0 && (c->mask & (WTD_TERM_K1D | WTD_TERM_K2D))) {
     c->tau = dalloc(c, tau_fields * nr * sizeof(T));
+    c->tau_fields = tau_fields;
+  }
+  if (c->alpha != 0.0 && (c->mask & WTD_TERM_K2D)) {
+    const int64_t nq = (int64_t)nocc * nocc;
+    c->k2_npk = (int)((nq + 1) / 2);
+    std::vector<int4> kq((size_t)mnb * c->k2_npk);
+    for (int b = 0; b < mnb; ++b) {
+      const int A = nocc + b * nocc;
+      for (int64_t k = 0; k < c->k2_npk; ++k) {
+        const int64_t q0 = 2 * k, q1 = 2 * k + 1;
+        int4 e{A + (int)(q0 / nocc), (int)(q0 % nocc), -1, -1};
+        if (q1 < nq) e.z = A + (int)(q1 / nocc), e.w = (int)(q1 % nocc);
+        kq[(size_t)b * c->k2_npk + k] = e;
+      }
+    }
+    c->k2quads = (int4*)dalloc(c, kq.size() * sizeof(int4));
+    h2d(c, c->k2quads, kq.data(), kq.size() * sizeof(int4));
+  }
   c->wst = dalloc(c, nwp * c->g.n0 * c->g.nws * sizeof(cplx<T>));
   // packed pairs per Poisson batch; the density-stick intermediate of one batch
   // is batch * n0 * n_d complex values (WTD_PAIR_CHUNK overrides the default)
@@ -549,16 +574,22 @@ void transform_occ(wtd_ctx* c, const double* c_occ) {
 
 // ---------------------------------------------------------------- the apply (steps 3-7)
 // Input: S [nb*nocc][nc] and a~ in G space (ag); output Q [nb*nocc][nc].
+// mask: the terms to apply (WTD_TERM_*; K2e and K2d only for the full operator).
+// At the Gamma point the trial fields are real, so K2e's density
+// sum_v' conj(a_v') phi_v' equals K1e's and the two add up to one response term.
 template <typename T>
-void apply_core(wtd_ctx* c, int nb) {
+void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   const Geometry& g = c->g;
   hipStream_t s = c->stream;
   const int nocc = c->nocc, npw = c->npw, nc = c->nc;
   const int K = 2 * npw;
-  const bool k1e = (c->mask & WTD_TERM_K1E) && c->ck != 0.0;
-  const bool k1d = (c->mask & WTD_TERM_K1D) && c->alpha != 0.0;
+  const int nresp = ((mask & WTD_TERM_K1E) ? 1 : 0) + ((mask & WTD_TERM_K2E) ? 1 : 0);
+  const double ck = c->ck * nresp;
+  const bool k1e = nresp > 0 && c->ck != 0.0;
+  const bool k1d = (mask & WTD_TERM_K1D) && c->alpha != 0.0;
+  const bool k2d = (mask & WTD_TERM_K2D) && c->alpha != 0.0;
   const int F = nb * nocc;
-  if (!k1e && !k1d) {
+  if (!k1e && !k1d && !k2d) {
     launch_zero<T>((T*)c->Q, (int64_t)F * nc, s);
     return;
   }
@@ -581,7 +612,7 @@ void apply_core(wtd_ctx* c, int nb) {
     // 5'-6'. R = response term, then the exchange sum block pair by block pair
     prof_next(c, 6);
     launch_response_rows<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->vh, (const T*)c->drho,
-                            (const T*)c->fxc, (T)c->ck, k1e, (T*)c->R, s);
+                            (const T*)c->fxc, (T)ck, k1e, (T*)c->R, s);
     if (k1d) {
       for (const auto& bp : c->bpairs) {
         for (int p0 = 0; p0 < bp.npack; p0 += c->pair_chunk) {
@@ -626,12 +657,44 @@ void apply_core(wtd_ctx* c, int nb) {
   // 6. R
   prof_next(c, 6);
   if (c->row_block) {
+  } else if (!k1e && !k1d) {
+    launch_zero<T>((T*)c->R, (int64_t)nb * nocc * g.nr, s);
   } else if (!launch_contract_mfma<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau,
-                               (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
+                               (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)ck,
                                (T)c->alpha, k1e, k1d, (T*)c->R, s))
     launch_contract<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau, c->pidx,
-                       (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)c->ck,
+                       (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)ck,
                        (T)c->alpha, k1e, k1d, (T*)c->R, s);
+  // 6b. K2d: R_bv -= alpha sum_v' phi_v' v_c * (a_bv' phi_v), trial by trial, in
+  // chunks of rows v' whose nocc pair fields fit in the pair-potential buffer
+  if (k2d) {
+    prof_next(c, 10);
+    c->tau_valid = false;
+    const int nfield_all = nocc * (1 + c->max_nb);
+    int rows = (int)std::min<size_t>((size_t)nocc, c->tau_fields / (size_t)nocc);
+    if (rows < nocc && (nocc & 1)) rows &= ~1;  // chunks start on whole packs
+    WTD_REQUIRE(rows >= 1, WTD_ERR_SHAPE, "pair buffer too small for one row of K2d pairs");
+    for (int b = 0; b < nb; ++b) {
+      const int4* kq = c->k2quads + (size_t)b * c->k2_npk;
+      for (int r0 = 0; r0 < nocc; r0 += rows) {
+        const int nrw = std::min(rows, nocc - r0);
+        const int nf = nrw * nocc;
+        const int k0 = (int)((int64_t)r0 * nocc / 2);
+        const int npk = (nf + 1) / 2;
+        for (int p0 = 0; p0 < npk; p0 += c->pair_chunk) {
+          const int np = std::min(c->pair_chunk, npk - p0);
+          const int nfs = std::min(2 * np, nf - 2 * p0);
+          launch_pairs_to_dsticks<T>(g, (const T*)c->phi, kq + k0 + p0, np, nfield_all,
+                                     (cplx<T>*)c->dst, s);
+          launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
+          launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nfs,
+                                      (T*)c->tau + (int64_t)2 * p0 * g.nr, s);
+        }
+        launch_k2d_rows<T>(g, nocc, nrw, r0, (const T*)c->phi, (const T*)c->tau, (T)c->alpha,
+                           (T*)c->R + (int64_t)b * nocc * g.nr, s);
+      }
+    }
+  }
   // 7. back to the sphere
   prof_next(c, 7);
   launch_fields_to_wsticks<T>(g, (const T*)c->R, nb, nocc, nocc, (cplx<T>*)c->wst, s);
@@ -645,7 +708,7 @@ void apply_core(wtd_ctx* c, int nb) {
 }
 
 template <typename T>
-void apply_impl(wtd_ctx* c, int nb, const T* a, T* la) {
+void apply_impl(wtd_ctx* c, int nb, const T* a, T* la, uint32_t mask) {
   hipStream_t s = c->stream;
   const int nocc = c->nocc, npw = c->npw, nc = c->nc;
   const int K = 2 * npw, F = nb * nocc;
@@ -653,17 +716,17 @@ void apply_impl(wtd_ctx* c, int nb, const T* a, T* la) {
   launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s,
                        (T*)c->gemm_scratch, c->gemm_scratch_elems);
   launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
-  apply_core<T>(c, nb);
+  apply_core<T>(c, nb, mask);
   prof_next(c, 8);
   launch_dterm_combine<T>(nb, nocc, nc, (const T*)c->S, (const T*)c->Q, c->eps_occ, c->eps_cond,
-                          (c->mask & WTD_TERM_D) != 0, (T*)c->Tm, s);
+                          (mask & WTD_TERM_D) != 0, (T*)c->Tm, s);
   launch_gemm<T, false>(F, K, nc, (const T*)c->Tm, nc, (const T*)c->c_cond, K, la, K, s);
   prof_end(c);
   prof_finish(c);
 }
 
 template <typename T>
-void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout) {
+void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout, uint32_t mask) {
   hipStream_t s = c->stream;
   const int nocc = c->nocc, npw = c->npw, nc = c->nc;
   const int K = 2 * npw, F = nb * nocc;
@@ -673,19 +736,22 @@ void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout) {
   else
     launch_convert<double, float>(X, (float*)c->S, (int64_t)F * nc, s);
   launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
-  apply_core<T>(c, nb);
+  apply_core<T>(c, nb, mask);
   prof_next(c, 8);
   launch_transition_out(nb, nocc, nc, c->Q, sizeof(T) == sizeof(float), X, c->eps_occ,
-                        c->eps_cond, (c->mask & WTD_TERM_D) != 0, Tout, s);
+                        c->eps_cond, (mask & WTD_TERM_D) != 0, Tout, s);
   prof_end(c);
   prof_finish(c);
 }
 
-void apply_transition_any(wtd_ctx* c, int nb, const double* X, double* T) {
+// the TDA operator: the context's D, K1e and K1d terms
+uint32_t tda_mask(const wtd_ctx* c) { return c->mask & WTD_TERM_ALL; }
+
+void apply_transition_any(wtd_ctx* c, int nb, const double* X, double* T, uint32_t mask) {
   if (c->prec == WTD_FP64)
-    apply_transition_impl<double>(c, nb, X, T);
+    apply_transition_impl<double>(c, nb, X, T, mask);
   else
-    apply_transition_impl<float>(c, nb, X, T);
+    apply_transition_impl<float>(c, nb, X, T, mask);
 }
 
 // ---------------------------------------------------------------- backward
@@ -727,7 +793,7 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
     // dE/da = W L (W^-1 g)
     WTD_HIP(hipMemcpyAsync(c->gbuf, g, (size_t)F * K * sizeof(T), hipMemcpyDeviceToDevice, s));
     launch_weights<T>((T*)c->gbuf, F, npw, 0, s);
-    apply_impl<T>(c, nb, (const T*)c->gbuf, g_a);
+    apply_impl<T>(c, nb, (const T*)c->gbuf, g_a, tda_mask(c));
     launch_weights<T>(g_a, F, npw, 1, s);
   }
   if (!g_occ) return;
@@ -844,11 +910,11 @@ void autotune_impl(wtd_ctx* c, int nb, int reps, int32_t* chunk_out, int32_t* gr
   c->prof.on = false;
   c->tau_cache = false;
   auto time_apply = [&]() {
-    apply_impl<T>(c, nb, (const T*)t.a, (T*)t.la);  // warm-up
+    apply_impl<T>(c, nb, (const T*)t.a, (T*)t.la, tda_mask(c));  // warm-up
     std::vector<float> ms(reps);
     for (int r = 0; r < reps; ++r) {
       WTD_HIP(hipEventRecord(t.e0, s));
-      apply_impl<T>(c, nb, (const T*)t.a, (T*)t.la);
+      apply_impl<T>(c, nb, (const T*)t.a, (T*)t.la, tda_mask(c));
       WTD_HIP(hipEventRecord(t.e1, s));
       WTD_HIP(hipEventSynchronize(t.e1));
       WTD_HIP(hipEventElapsedTime(&ms[r], t.e0, t.e1));
@@ -1007,7 +1073,7 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
 
   int added = orthonormalise_append(nb);
   WTD_REQUIRE(added > 0, WTD_ERR_ARG, "Davidson guess block is rank deficient");
-  apply_transition_any(c, added, V, W);
+  apply_transition_any(c, added, V, W, tda_mask(c));
   m = added;
   int it = 0;
   bool converged = false;
@@ -1042,7 +1108,7 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
     }
     const int na = orthonormalise_append((int)act.size());
     if (na == 0) break;
-    apply_transition_any(c, na, V + (int64_t)m * n, W + (int64_t)m * n);
+    apply_transition_any(c, na, V + (int64_t)m * n, W + (int64_t)m * n, tda_mask(c));
     m += na;
   }
   const int nr_out = std::min(nroots, kcur);
@@ -1063,6 +1129,106 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
       launch_gemm<double, false>(nr_out * nocc, K, nc, Xr, nc, Cd, K, x, K, s);
     }
   }
+  WTD_HIP(hipStreamSynchronize(s));
+  return converged ? WTD_OK : WTD_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------- Z-vector CG (FP64)
+// CG on the full operator in transition coordinates, nrhs systems side by side
+// sharing one apply per iteration; K2d is dropped from the first iteration at
+// which every unconverged residual norm is below lambda_thr (inexact Krylov).
+wtd_status zvector_impl(wtd_ctx* c, int nrhs, const double* U, double tol, int max_iter,
+                        double lambda_thr, double* Z, double* resid, int32_t* n_iter,
+                        int32_t* n_exact) {
+  hipStream_t s = c->stream;
+  const int nocc = c->nocc, nc = c->nc, npw = c->npw, K = 2 * npw;
+  const int64_t n = (int64_t)nocc * nc;
+  DavWork w{c, {}};
+  struct KeepPairs {
+    wtd_ctx* c;
+    bool saved;
+    ~KeepPairs() {
+      c->tau_cache = saved;
+      if (!saved) c->tau_valid = false;
+    }
+  } keep{c, c->tau_cache};
+  if (!c->row_block) c->tau_cache = true;
+  double* zt = w.alloc((size_t)nrhs * n);
+  double* r = w.alloc((size_t)nrhs * n);
+  double* p = w.alloc((size_t)nrhs * n);
+  double* ap = w.alloc((size_t)nrhs * n);
+  double* dots = w.alloc(nrhs);
+  double* coef = w.alloc(nrhs);
+  // right-hand sides in transition coordinates: b = Phi_c^T W U
+  const double* cw = (const double*)c->c_condw;
+  const double* cc = (const double*)c->c_cond;
+  if (c->prec != WTD_FP64) {
+    double* Cw = w.alloc((size_t)nc * K);
+    double* Cd = w.alloc((size_t)nc * K);
+    launch_convert<float, double>((const float*)c->c_condw, Cw, (int64_t)nc * K, s);
+    launch_convert<float, double>((const float*)c->c_cond, Cd, (int64_t)nc * K, s);
+    cw = Cw;
+    cc = Cd;
+  }
+  launch_gemm<double, true>(nrhs * nocc, nc, K, U, K, cw, K, r, nc, s);
+  launch_zero<double>(zt, (int64_t)nrhs * n, s);
+  WTD_HIP(hipMemcpyAsync(p, r, (size_t)nrhs * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> rr(nrhs), pap(nrhs), rn(nrhs), hc(nrhs);
+  launch_col_norms(r, nrhs, n, dots, s);
+  WTD_HIP(hipMemcpyAsync(rr.data(), dots, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  WTD_HIP(hipStreamSynchronize(s));
+  std::vector<char> active(nrhs);
+  auto update_active = [&]() {
+    bool any = false;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!std::isfinite(rr[k])) throw StatusError{WTD_ERR_NONFINITE, "non-finite CG residual"};
+      active[k] = std::sqrt(rr[k]) > tol;
+      any = any || active[k];
+    }
+    return any;
+  };
+  bool use_exact = true;
+  int it = 0, nex = 0;
+  while (update_active() && it < max_iter) {
+    if (use_exact && lambda_thr > 0.0) {
+      bool below = true;
+      for (int k = 0; k < nrhs; ++k)
+        if (active[k] && !(std::sqrt(rr[k]) < lambda_thr)) below = false;
+      if (below) use_exact = false;
+    }
+    apply_transition_any(c, nrhs, p, ap, use_exact ? c->mask : (c->mask & ~WTD_TERM_K2D));
+    nex += use_exact ? 1 : 0;
+    launch_col_dots(p, ap, nrhs, n, dots, s);
+    WTD_HIP(hipMemcpyAsync(pap.data(), dots, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nrhs; ++k) {
+      hc[k] = 0.0;
+      if (!active[k]) continue;
+      WTD_REQUIRE(pap[k] > 0.0 && std::isfinite(pap[k]), WTD_ERR_NONFINITE,
+                  "CG breakdown: the operator is not positive definite on the search direction");
+      hc[k] = rr[k] / pap[k];
+    }
+    h2d(c, coef, hc.data(), nrhs * sizeof(double));
+    launch_cg_update(zt, r, p, ap, coef, nrhs, n, s);
+    launch_col_norms(r, nrhs, n, dots, s);
+    WTD_HIP(hipMemcpyAsync(rn.data(), dots, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < nrhs; ++k) {
+      hc[k] = active[k] ? rn[k] / rr[k] : 0.0;
+      if (active[k]) rr[k] = rn[k];
+    }
+    h2d(c, coef, hc.data(), nrhs * sizeof(double));
+    // frozen systems: beta = 0 turns p into r, which their zero step ignores
+    launch_cg_direction(p, r, coef, nrhs, n, s);
+    ++it;
+  }
+  bool converged = !update_active();
+  for (int k = 0; k < nrhs; ++k)
+    if (resid) resid[k] = std::sqrt(rr[k]);
+  if (n_iter) *n_iter = it;
+  if (n_exact) *n_exact = nex;
+  // Z = Phi_c z in G space
+  launch_gemm<double, false>(nrhs * nocc, K, nc, zt, nc, cc, K, Z, K, s);
   WTD_HIP(hipStreamSynchronize(s));
   return converged ? WTD_OK : WTD_NOT_CONVERGED;
 }
@@ -1105,7 +1271,7 @@ wtd_status wtd_create(const wtd_system* sys, int32_t max_nb, void* hip_stream, w
     WTD_REQUIRE(sys->cell[0] > 0 && sys->cell[1] > 0 && sys->cell[2] > 0, WTD_ERR_ARG,
                 "cell lengths must be positive");
     WTD_REQUIRE(sys->prec == WTD_FP64 || sys->prec == WTD_FP32, WTD_ERR_ARG, "bad precision");
-    WTD_REQUIRE((sys->term_mask & ~7u) == 0, WTD_ERR_ARG, "bad term mask");
+    WTD_REQUIRE((sys->term_mask & ~31u) == 0, WTD_ERR_ARG, "bad term mask");
     WTD_REQUIRE(std::isfinite(sys->alpha) && std::isfinite(sys->k1e_scale) &&
                     std::isfinite(sys->v_g0),
                 WTD_ERR_ARG, "non-finite scalar parameter");
@@ -1194,10 +1360,36 @@ wtd_status wtd_apply_liouville(wtd_ctx* ctx, int32_t nb, const void* a, void* la
     WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
     WTD_REQUIRE(a != la, WTD_ERR_ARG, "a and la must not alias");
     if (ctx->prec == WTD_FP64)
-      apply_impl<double>(ctx, nb, (const double*)a, (double*)la);
+      apply_impl<double>(ctx, nb, (const double*)a, (double*)la, tda_mask(ctx));
     else
-      apply_impl<float>(ctx, nb, (const float*)a, (float*)la);
+      apply_impl<float>(ctx, nb, (const float*)a, (float*)la, tda_mask(ctx));
     return WTD_OK;
+  });
+}
+
+wtd_status wtd_apply_full(wtd_ctx* ctx, int32_t nb, const void* a, void* la) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && a && la, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
+    WTD_REQUIRE(a != la, WTD_ERR_ARG, "a and la must not alias");
+    if (ctx->prec == WTD_FP64)
+      apply_impl<double>(ctx, nb, (const double*)a, (double*)la, ctx->mask);
+    else
+      apply_impl<float>(ctx, nb, (const float*)a, (float*)la, ctx->mask);
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_solve_zvector(wtd_ctx* ctx, int32_t nrhs, const double* U, double tol,
+                             int32_t max_iter, double lambda_thr, double* Z, double* resid,
+                             int32_t* n_iter, int32_t* n_exact) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && U && Z, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nrhs >= 1 && nrhs <= ctx->max_nb, WTD_ERR_SHAPE, "nrhs out of range [1, max_nb]");
+    WTD_REQUIRE(max_iter >= 1 && tol > 0.0 && lambda_thr >= 0.0, WTD_ERR_ARG,
+                "need max_iter >= 1, tol > 0 and lambda_thr >= 0");
+    WTD_REQUIRE((const void*)U != (void*)Z, WTD_ERR_ARG, "U and Z must not alias");
+    return zvector_impl(ctx, nrhs, U, tol, max_iter, lambda_thr, Z, resid, n_iter, n_exact);
   });
 }
 
@@ -1206,7 +1398,7 @@ wtd_status wtd_apply_transition(wtd_ctx* ctx, int32_t nb, const double* X, doubl
     WTD_REQUIRE(ctx && X && T, WTD_ERR_ARG, "null argument");
     WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
     WTD_REQUIRE((const void*)X != (void*)T, WTD_ERR_ARG, "X and T must not alias");
-    apply_transition_any(ctx, nb, X, T);
+    apply_transition_any(ctx, nb, X, T, tda_mask(ctx));
     return WTD_OK;
   });
 }

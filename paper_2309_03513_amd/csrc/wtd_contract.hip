@@ -971,6 +971,42 @@ void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, con
   WTD_HIP(hipGetLastError());
 }
 
+namespace {
+// One thread per (grid point, row v): the point's sum over the chunk's rows v'
+// reads W once, coalesced along the grid; phi_v'(r) is shared by the nocc
+// workgroups of one point range and comes from L2.  Memory-bound: no reuse of
+// W across points, so no matrix-core tiling.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_k2d_rows(int64_t nr, int nocc, int nrows, int r0, const T* __restrict__ phi,
+           const T* __restrict__ W, T alpha, T* __restrict__ R) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (r >= nr) return;
+  T acc = T(0);
+  const T* w = W + (int64_t)v * nr + r;
+  const T* f = phi + (int64_t)r0 * nr + r;
+  for (int j = 0; j < nrows; ++j) acc += f[(int64_t)j * nr] * w[(int64_t)j * nocc * nr];
+  R[(int64_t)v * nr + r] -= alpha * acc;
+}
+}  // namespace
+
+template <typename T>
+void launch_k2d_rows(const Geometry& g, int nocc, int nrows, int r0, const T* phi, const T* W,
+                     T alpha, T* R, hipStream_t s) {
+  WTD_REQUIRE(nocc >= 1 && nocc <= 65535 && nrows >= 1 && r0 >= 0 && r0 + nrows <= nocc,
+              WTD_ERR_SHAPE, "K2d row chunk out of range");
+  dim3 grid((unsigned)((g.nr + 255) / 256), (unsigned)nocc);
+  hipLaunchKernelGGL(k_k2d_rows<T>, grid, dim3(256), 0, s, g.nr, nocc, nrows, r0, phi, W, alpha,
+                     R);
+  WTD_HIP(hipGetLastError());
+}
+
+template void launch_k2d_rows<float>(const Geometry&, int, int, int, const float*, const float*,
+                                     float, float*, hipStream_t);
+template void launch_k2d_rows<double>(const Geometry&, int, int, int, const double*,
+                                      const double*, double, double*, hipStream_t);
+
 template void launch_response_rows<float>(const Geometry&, int, int, const float*, const float*,
                                           const float*, const float*, float, bool, float*,
                                           hipStream_t);

@@ -106,6 +106,42 @@ k_row_norm2(const double* __restrict__ t, int64_t n, double* __restrict__ out) {
   if (threadIdx.x == 0) out[j] = s;
 }
 
+__global__ void __launch_bounds__(kRed)
+k_row_dot(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+          double* __restrict__ out) {
+  __shared__ double sh[kRed];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x)
+    s += a[(int64_t)j * n + r] * b[(int64_t)j * n + r];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+// conjugate-gradient updates of k independent systems, step sizes per row:
+// z_j += alpha_j p_j, r_j -= alpha_j Ap_j
+__global__ void k_cg_update(double* __restrict__ z, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ ap,
+                            const double* __restrict__ alpha, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  const int64_t o = (int64_t)j * n + i;
+  const double a = alpha[j];
+  z[o] += a * p[o];
+  r[o] -= a * ap[o];
+}
+
+// p_j = r_j + beta_j p_j
+__global__ void k_cg_direction(double* __restrict__ p, const double* __restrict__ r,
+                               const double* __restrict__ beta, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  const int64_t o = (int64_t)j * n + i;
+  p[o] = r[o] + beta[j] * p[o];
+}
+
 __global__ void k_scale_row(double* __restrict__ t, double f, int64_t n) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) t[r] *= f;
@@ -286,6 +322,27 @@ void launch_axpy_cols(double* t, const double* V, const double* coef, int m, int
 void launch_col_norms(const double* t, int k, int64_t n, double* out, hipStream_t s) {
   if (k <= 0) return;
   hipLaunchKernelGGL(k_row_norm2, dim3(k), dim3(kRed), 0, s, t, n, out);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_col_dots(const double* a, const double* b, int k, int64_t n, double* out,
+                     hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_row_dot, dim3(k), dim3(kRed), 0, s, a, b, n, out);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_cg_update(double* z, double* r, const double* p, const double* ap,
+                      const double* alpha, int k, int64_t n, hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_cg_update, rows_grid(n, k), dim3(256), 0, s, z, r, p, ap, alpha, n);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_cg_direction(double* p, const double* r, const double* beta, int k, int64_t n,
+                         hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_cg_direction, rows_grid(n, k), dim3(256), 0, s, p, r, beta, n);
   WTD_HIP(hipGetLastError());
 }
 

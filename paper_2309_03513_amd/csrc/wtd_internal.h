@@ -119,6 +119,13 @@ template <typename T>
 void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, const T* tau, int A0,
                            int nA, int B0, int nB, bool diag, T alpha, T* R, hipStream_t s);
 
+// K2d contraction of one trial (wtd_contract.hip): for rows v' in [r0, r0 + nrows),
+// R[v] -= alpha sum_v' phi_v' W[(v' - r0) nocc + v], W the Poisson-solved products
+// a_v' phi_v stored [pair][N_r].
+template <typename T>
+void launch_k2d_rows(const Geometry& g, int nocc, int nrows, int r0, const T* phi, const T* W,
+                     T alpha, T* R, hipStream_t s);
+
 // Backward kernels (wtd_backward.hip).
 // Pair densities of rows [A0, A0 + nA) x [B0, B0 + nB) (diag: the upper
 // triangle of one block), stored in the block layout of the pair pipeline.
@@ -167,5 +174,12 @@ void launch_axpy_cols(double* t, const double* V, const double* coef, int m, int
                       hipStream_t s);
 void launch_col_norms(const double* t, int k, int64_t n, double* out, hipStream_t s);
 void launch_scale_rows(double* t, double f, int64_t n, hipStream_t s);
+// rows of k x n arrays: out[j] = a_j . b_j; CG steps with per-row coefficients
+void launch_col_dots(const double* a, const double* b, int k, int64_t n, double* out,
+                     hipStream_t s);
+void launch_cg_update(double* z, double* r, const double* p, const double* ap,
+                      const double* alpha, int k, int64_t n, hipStream_t s);
+void launch_cg_direction(double* p, const double* r, const double* beta, int k, int64_t n,
+                         hipStream_t s);
 
 }  // namespace wtd

@@ -23,9 +23,10 @@ STATUS_NAMES = {0: "WTD_OK", 1: "WTD_NOT_CONVERGED", -1: "WTD_ERR_ARG", -2: "WTD
                 -6: "WTD_ERR_NONFINITE"}
 FP64, FP32 = 0, 1
 TERM_D, TERM_K1E, TERM_K1D, TERM_ALL = 1, 2, 4, 7
+TERM_K2E, TERM_K2D, TERM_FULL = 8, 16, 31
 
 EXPORTS = ["wtd_debug_gemm", "wtd_create", "wtd_destroy", "wtd_set_occ", "wtd_apply_liouville",
-           "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson", "wtd_cache_pairs", "wtd_autotune",
+           "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson", "wtd_cache_pairs", "wtd_autotune", "wtd_apply_full", "wtd_solve_zvector",
            "wtd_profile_enable", "wtd_profile_read", "wtd_workspace_bytes", "wtd_last_error"]
 
 
@@ -76,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     lib.wtd_apply_liouville_bwd.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.wtd_davidson.argtypes = [vp, i32, i32, f64, i32, i32, vp, vp, vp, vp, vp]
     lib.wtd_cache_pairs.argtypes = [vp, i32]
+    lib.wtd_apply_full.argtypes = [vp, i32, vp, vp]
+    lib.wtd_solve_zvector.argtypes = [vp, i32, vp, f64, i32, f64, vp, vp, vp, vp]
     lib.wtd_autotune.argtypes = [vp, i32, i32, vp, vp]
     lib.wtd_profile_enable.argtypes = [vp, i32]
     lib.wtd_profile_read.argtypes = [vp, i32, vp, vp, vp, vp]
@@ -200,6 +203,32 @@ class Liouville:
             out = torch.empty_like(a)
         _check(self._lib.wtd_apply_liouville(self._handle(), nb, _ptr(a), _ptr(out)))
         return out
+
+    def apply_full(self, a, out=None):
+        """la = (D + K1e - K1d + K2e - K2d) a with the context's term mask."""
+        torch = _torch()
+        if not (isinstance(a, torch.Tensor) and a.dtype == self.dtype and a.is_contiguous()
+                and a.device == self.device and a.dim() == 4):
+            a = as_coeff_tensor(a, self.dtype, self.device)
+        assert tuple(a.shape[1:]) == (self.nocc, self.npw, 2), a.shape
+        if out is None:
+            out = torch.empty_like(a)
+        _check(self._lib.wtd_apply_full(self._handle(), a.shape[0], _ptr(a), _ptr(out)))
+        return out
+
+    def solve_zvector(self, U, tol=1e-8, max_iter=200, lambda_thr=0.0):
+        """CG solve of the Z-vector equation; returns (Z float64 tensor, resid numpy,
+        n_iter, n_exact, status)."""
+        torch = _torch()
+        U = as_coeff_tensor(U, torch.float64, self.device)
+        Z = torch.empty_like(U)
+        resid = np.zeros(U.shape[0])
+        nit, nex = ctypes.c_int32(), ctypes.c_int32()
+        st = _check(self._lib.wtd_solve_zvector(
+            self._handle(), U.shape[0], _ptr(U), float(tol), int(max_iter), float(lambda_thr),
+            _ptr(Z), resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nit),
+            ctypes.byref(nex)))
+        return Z, resid, nit.value, nex.value, st
 
     def apply_transition(self, X, out=None):
         """T = Phi_c^T L Phi_c X; X: [nb][nocc][ncond] float64 device tensor."""
