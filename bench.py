@@ -33,10 +33,10 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 843.4e6,
+        "bytes": 868.3e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "ebae947baffb38e3ec2490041cd98151f40651b2f255ac63125b938c4b171613",
+                "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -44,10 +44,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1299.8e6,
+        "bytes": 1300.3e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "ebae947baffb38e3ec2490041cd98151f40651b2f255ac63125b938c4b171613",
+                "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -55,10 +55,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_plane_inv": {
-        "bytes": 1988.6e6,
+        "bytes": 1988.7e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "ebae947baffb38e3ec2490041cd98151f40651b2f255ac63125b938c4b171613",
+                "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -66,10 +66,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "contract": {
-        "bytes": 19662.4e6,
+        "bytes": 19678.3e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "044d7cb51965de0b2a32862e2eab3898fc5ad437aacf8fbf81b7f3ecb53eb34a",
+                "cd044aac443429e09c6706a53d41b8929f6bb010a148502bbf988dd741f5cb8a",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
         },
@@ -168,6 +168,34 @@ def run_cached(L, a, out, nb, steps):
     return ms
 
 
+def run_full(s, nb, steps, a_np):
+    """Applies of the full operator D + K1e - K1d + K2e - K2d (FP32 bulk) and, for
+    scale, of its parts: per-block time of K2d, which dominates it."""
+    import torch
+    from paper_2309_03513_amd import Liouville
+    from paper_2309_03513_amd.wtd import TERM_FULL
+    L = Liouville(s, max_nb=nb, precision="fp32", terms=TERM_FULL)
+    a = torch.tensor(np.stack([a_np.real, a_np.imag], -1), dtype=torch.float32,
+                     device="cuda").contiguous()
+    out = torch.empty_like(a)
+    L.apply_full(a, out=out)
+    torch.cuda.synchronize()
+    L.profile(True)
+    L.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        L.apply_full(a, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = L.profile_read()
+    L.profile(False)
+    L.close()
+    k2d = st.get("k2d", (0.0, 0))[0] / steps
+    log(f"fp32 full operator: {ms:.1f} ms/block, {nb * 1e3 / ms:.1f} applies/s (K2d {k2d:.1f} ms)")
+    return {"value": nb * 1e3 / ms, "unit": "trial-vector applies/s", "ms_per_step": ms,
+            "k2d_ms_per_step": k2d, "steps": steps}
+
+
 def model_bytes(s, nb, sz):
     """Bytes per block of the path's byte model (2-pass FFT, maximal fusion, tau per
     pair written once and read once): trial fields written, density reads, pair
@@ -239,6 +267,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--full-steps", type=int, default=2,
+                    help="timed applies of the full Z-vector operator (0: skip)")
     ap.add_argument("--no-cached", action="store_true",
                     help="skip the extra timing with the pair potentials kept between applies")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -302,6 +332,10 @@ def main():
     if s.nocc > 128 or cfg.name != "c2":
         roofline = None
 
+    full = None
+    if args.full_steps > 0 and s.nocc <= 128:
+        full = run_full(s, nb, args.full_steps, a_np)
+        torch.cuda.empty_cache()
     acc = None if args.no_accuracy or cfg.name != "c2" else accuracy_fp32(s, nb, cfg.nroots)
     cpu = None if args.no_cpu else cpu_baseline(s, nb, a_np)
 
@@ -326,6 +360,7 @@ def main():
         "fp64": ({"value": nb * 1e3 / res["fp64"]["ms"], "ms_per_step": res["fp64"]["ms"],
                   "per_apply_ms": res["fp64"]["per_apply"]}
                  if "fp64" in res else None),
+        "full_operator": full,
         "pairs_kept": ({"value": nb * 1e3 / cached_ms, "ms_per_step": cached_ms,
                         "note": "pair potentials formed once and reused (Davidson setting); "
                                 "not the headline, which recomputes them every apply"}
