@@ -8,5 +8,5 @@ Poisson kernel, no Liouville terms).
 """
 from .systems import (  # noqa: F401
     Config, CONFIGS, System, half_sphere, make_system, trials_in_span,
-    trials_random, plane_wave_pair_system,
+    trials_random, plane_wave_pair_system, batch_configs,
 )

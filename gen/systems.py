@@ -25,7 +25,9 @@ not available, so every workload is synthetic.  The recipe:
 
 These choices stand in for the paper's NV- supercells: the 72^3 / Nocc = 128
 system has the size of the 63-atom (2x2x2) diamond cell used for the gradient
-tests, the 108^3 / Nocc = 432 system that of the 215-atom cell.
+tests, the 108^3 / Nocc = 432 system that of the 215-atom cell.  A batch of
+heterogeneous systems (batch_configs) mixes grids of 48^3 to 96^3 at the same
+grid spacing with 32 to 256 occupied orbitals.
 """
 from __future__ import annotations
 
@@ -86,6 +88,25 @@ CONFIGS = {
     "p4": Config("p4", *_cubic(12.0, 36), ecut_ry=20.0, nocc=144, ncond=24, gap=0.15,
                  nb=3, nroots=3, seed=14),
 }
+
+
+BATCH_GRIDS = (48, 60, 72, 96)
+
+
+def batch_configs(count: int = 12, seed: int = 4000):
+    """Heterogeneous batch of systems: for i < count, a grid n from
+    {48, 60, 72, 96} (cubic cell L = 0.1875 n bohr, the 72^3 system's spacing,
+    40 Ry), Nocc and Nc uniform in [32, 256], a trial block of 4..32 vectors,
+    all drawn from rng(seed); system i is generated with seed 400 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(BATCH_GRIDS))
+        nocc = int(rng.integers(32, 257))
+        nb = int(rng.integers(4, 33))
+        out.append(Config(f"b{i:02d}", *_cubic(0.1875 * n, n), ecut_ry=40.0, nocc=nocc,
+                          ncond=nocc, gap=0.15, nb=nb, nroots=min(4, nb), seed=400 + i))
+    return out
 
 
 @dataclasses.dataclass
@@ -234,7 +255,10 @@ def trials_in_span(sys: System, nb: int, seed: int | None = None):
     x = rng.standard_normal((nb, sys.nocc, sys.ncond))
     x /= np.sqrt(np.sum(x * x, axis=(1, 2)))[:, None, None]
     xf = x.reshape(-1, sys.ncond)
-    a = (xf @ sys.c_cond.real + 1j * (xf @ sys.c_cond.imag)).reshape(nb, sys.nocc, -1)
+    # contiguous copies of the real and imaginary parts keep the products on BLAS
+    cr = np.ascontiguousarray(sys.c_cond.real)
+    ci = np.ascontiguousarray(sys.c_cond.imag)
+    a = (xf @ cr + 1j * (xf @ ci)).reshape(nb, sys.nocc, -1)
     return a, x
 
 
