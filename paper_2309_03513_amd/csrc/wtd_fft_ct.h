@@ -5,8 +5,9 @@
 // applied odd radices first, then even ones, each group ascending: the first
 // pass (p = 1) writes with a stride equal to its radix, and an odd stride keeps
 // LDS bank conflicts low.
-// Twiddles are read from an LDS copy of the FP64-generated table
-// tw[j] = exp(-2 pi i j / N), j < N.
+// Twiddles come from an LDS copy of the FP64-generated table
+// tw[j] = exp(-2 pi i j / N), j < N: w and w^2 of each butterfly are read, the
+// higher powers formed by complex products.
 #pragma once
 #include "wtd_fft.h"
 
@@ -93,13 +94,20 @@ __device__ __forceinline__ void ct_pass(cplx<T>* buf, const cplx<T>* tw) {
         const int i = LF ? b / NL : b % M;
         const int k = i % P;
         cplx<T>* base = buf + line * LS;
+        // twiddle powers w^t: w and w^2 from the table, the rest as products of
+        // two lower powers (at most two roundings deep for radices up to 9),
+        // which saves LDS reads in the passes after the first
+        cplx<T> wp[R];
+        if constexpr (P > 1) {
+          wp[1] = tw[k * TWS];
+          if constexpr (R > 2) wp[2] = tw[2 * k * TWS];
+#pragma unroll
+          for (int t = 3; t < R; ++t) wp[t] = cmul(wp[t / 2], wp[t - t / 2]);
+        }
 #pragma unroll
         for (int t = 0; t < R; ++t) {
           cplx<T> x = base[(i + t * M) * ES];
-          if (P > 1 && t > 0) {
-            const cplx<T> w = tw[t * k * TWS];
-            x = (S < 0) ? cmul(x, w) : cmulc(x, w);
-          }
+          if (P > 1 && t > 0) x = (S < 0) ? cmul(x, wp[t]) : cmulc(x, wp[t]);
           v[u][t] = x;
         }
         ct_dft<R, S>(v[u]);
