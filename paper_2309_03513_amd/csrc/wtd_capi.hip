@@ -511,10 +511,10 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->drho = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->vh = dalloc(c, (size_t)mnb * nr * sizeof(T));
   c->drho_part = dalloc(c, (size_t)kDrhoGroups * mnb * nr * sizeof(T));
-  // (all pairs: rounded up to whole groups of 8 for the interleaved layout)
+  // (rounded up to whole groups of 8 for the interleaved layout)
   const size_t tau_fields =
-      c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs)
-                   : ((size_t)c->npairs + 7) / 8 * 8;
+      ((c->row_block ? std::min<size_t>((size_t)c->row_block * c->row_block, c->npairs)
+                     : (size_t)c->npairs) + 7) / 8 * 8;
   if (c->alpha != 0.0 && (c->mask & (WTD_TERM_K1D | WTD_TERM_K2D))) {
     c->tau = dalloc(c, tau_fields * nr * sizeof(T));
     c->tau_fields = tau_fields;
@@ -543,8 +543,10 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->pair_chunk = std::max(1, std::min(c->npack_pairs, chunk));
   // chunks start on whole groups of 8 fields (4 packs) for the interleaved layout
   if (c->pair_chunk >= 4) c->pair_chunk = c->pair_chunk / 4 * 4;
-  if (c->row_block)
+  if (c->row_block) {
     c->pair_chunk = std::min(c->pair_chunk, (int)((tau_fields + 1) / 2));
+    if (c->pair_chunk >= 4) c->pair_chunk = c->pair_chunk / 4 * 4;
+  }
   c->max_pair_chunk = c->pair_chunk;
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
   c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nds * sizeof(cplx<T>));
@@ -614,6 +616,13 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
     launch_response_rows<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->vh, (const T*)c->drho,
                             (const T*)c->fxc, (T)ck, k1e, (T*)c->R, s);
     if (k1d) {
+      // FP32 with whole 16-trial tiles: pair potentials in the interleaved layout
+      // and the register-operand block contraction
+      const bool bil = contract_block_rr_applies<T>(nb);
+      int max_npack = 0;
+      for (const auto& bp : c->bpairs) max_npack = std::max(max_npack, bp.npack);
+      WTD_REQUIRE(!bil || c->pair_chunk % 2 == 0 || c->pair_chunk >= max_npack, WTD_ERR_SHAPE,
+                  "pair chunk must start on whole groups of 4 pairs");
       for (const auto& bp : c->bpairs) {
         for (int p0 = 0; p0 < bp.npack; p0 += c->pair_chunk) {
           const int np = std::min(c->pair_chunk, bp.npack - p0);
@@ -625,11 +634,16 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
           launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
           prof_next(c, 5);
           launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
-                                      (T*)c->tau + (int64_t)2 * p0 * g.nr, s);
+                                      (T*)c->tau + (int64_t)2 * p0 * g.nr, s, bil);
         }
         prof_next(c, 6);
-        launch_contract_block<T>(g, nb, nocc, (const T*)c->at, (const T*)c->tau, bp.A0, bp.nA,
-                                 bp.B0, bp.nB, bp.diag != 0, (T)c->alpha, (T*)c->R, s);
+        if (bil)
+          launch_contract_block_rr<T>(g, nb, nocc, (const T*)c->at, (const T*)c->tau, bp.A0,
+                                      bp.nA, bp.B0, bp.nB, bp.diag != 0, (T)c->alpha, (T*)c->R,
+                                      s);
+        else
+          launch_contract_block<T>(g, nb, nocc, (const T*)c->at, (const T*)c->tau, bp.A0, bp.nA,
+                                   bp.B0, bp.nB, bp.diag != 0, (T)c->alpha, (T*)c->R, s);
       }
     }
   }

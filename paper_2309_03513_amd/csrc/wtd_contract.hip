@@ -972,6 +972,199 @@ void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, con
 }
 
 namespace {
+// ---------------------------------------------------------------------------
+// Row-blocked contraction, FP32, trial fields in registers.  A workgroup owns 8
+// grid points (one per wave) and 32 trials of one block pair (A, B): every wave
+// first takes the MFMA operand fragments of a[A] and a[B] (16 x 16 tiles, both
+// trial tiles) for its point into registers, then walks the block's tau tiles
+// once, staged through LDS with the next tile's loads in flight, and adds
+// R[A] += tau a[B] and R[B] += tau^T a[A] (upper-triangle tiles and
+// R[A] += tau a[A] on the diagonal block) into accumulators that are written
+// back once: tau is read once for all trials and a once per block pair.
+// tau is in the 4-pair interleaved layout: block-local pair P at point r is
+// element ((P / 4) N_r + r) 4 + P % 4.
+struct BRTile {
+  static constexpr int TP = 8;
+  static constexpr int THREADS = 512;
+  static constexpr int NE = 256 * TP;  // one 16 x 16 tile for TP points
+  static __device__ __forceinline__ int at(int q, int p) {
+    const int h = (q >> 4) + 17 * (q & 15);
+    return q * TP + ((p + h) & (TP - 1));
+  }
+};
+
+template <bool DIAG>
+__device__ __forceinline__ void br_load_tau(float (&pf)[4], const float* __restrict__ tau,
+                                            int I, int J, const BArgs& bk, int64_t nr,
+                                            int64_t r0) {
+  const int nJ = DIAG ? bk.nA : bk.nB;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * BRTile::THREADS;
+    const int p = (e >> 2) & 7, quad = e >> 5;
+    const int i = I * 16 + (quad >> 2), j = J * 16 + (quad & 3) * 4 + (e & 3);
+    const int64_t r = r0 + p;
+    float v = 0.f;
+    if (r < nr && i < bk.nA && j < nJ) {
+      const int64_t P = block_pair<float>(bk, i, j);
+      v = tau[(((P >> 2) * nr + r) << 2) + (P & 3)];
+    }
+    pf[u] = v;
+  }
+}
+
+__device__ __forceinline__ void br_store_tau(float* s, const float (&pf)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * BRTile::THREADS;
+    const int p = (e >> 2) & 7, quad = e >> 5;
+    const int q = (quad >> 2) * 16 + (quad & 3) * 4 + (e & 3);
+    s[BRTile::at(q, p)] = pf[u];
+  }
+}
+
+// tile n of the walk -> (I, J): the 4 x 4 rectangle row by row, or the upper
+// triangle I <= J row by row on the diagonal block
+template <bool DIAG>
+__device__ __forceinline__ constexpr int br_tile_i(int n) {
+  if (!DIAG) return n >> 2;
+  int i = 0;
+  while (n >= 4 - i) n -= 4 - i, ++i;
+  return i;
+}
+template <bool DIAG>
+__device__ __forceinline__ constexpr int br_tile_j(int n) {
+  if (!DIAG) return n & 3;
+  int i = 0;
+  while (n >= 4 - i) n -= 4 - i, ++i;
+  return i + n;
+}
+
+template <bool DIAG>
+__global__ void __launch_bounds__(BRTile::THREADS)
+k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ at,
+                    const float* __restrict__ tau, BArgs bk, float alpha,
+                    float* __restrict__ R) {
+  typedef Mfma<float>::acc_t acc_t;
+  constexpr int NS = DIAG ? 1 : 2;  // row blocks with accumulators: A (and B)
+  constexpr int NRT = 4 * NS;       // row tiles of a and R the workgroup touches
+  constexpr int NTILE = DIAG ? 10 : 16;
+  constexpr int PD = 3;             // tau tiles in flight ahead of the current one
+  __shared__ float s_a[2 * BRTile::NE];
+  __shared__ float s_t[2][BRTile::NE];
+  const int per = (ntile + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntile) return;
+  const int b0 = blockIdx.y * 32;
+  const int64_t r0 = (int64_t)tile * BRTile::TP;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lx = lane & 15, ly = lane >> 4;
+  const int base[2] = {bk.A0, DIAG ? bk.A0 : bk.B0};
+  const int nrow[2] = {bk.nA, DIAG ? bk.nA : bk.nB};
+  // element u of this thread in a 16-row x 32-trial x 8-point slab of a or R
+  auto slab_ok = [&](int rt, int u) {
+    const int e = threadIdx.x + u * BRTile::THREADS;
+    const int sd = rt >> 2, v = (rt & 3) * 16 + (e >> 8);
+    return v < nrow[sd] && b0 + ((e >> 3) & 31) < nb && r0 + (e & 7) < nr;
+  };
+  auto slab_off = [&](int rt, int u) {
+    const int e = threadIdx.x + u * BRTile::THREADS;
+    const int sd = rt >> 2, v = (rt & 3) * 16 + (e >> 8);
+    return ((int64_t)(b0 + ((e >> 3) & 31)) * nocc + base[sd] + v) * nr + r0 + (e & 7);
+  };
+  auto slab_lds = [&](int u) {
+    const int e = threadIdx.x + u * BRTile::THREADS;
+    const int b = (e >> 3) & 31;
+    return (b >> 4) * BRTile::NE + BRTile::at((e >> 8) * 16 + (b & 15), e & 7);
+  };
+
+  // 1. every a load of the workgroup in flight at once, then the operand
+  // fragments y[row tile][trial tile][k] = a[row 4k + ly][trial lx] per wave
+  float la[NRT][8];
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) la[rt][u] = slab_ok(rt, u) ? at[slab_off(rt, u)] : 0.f;
+  float y[NRT][2][4];
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s_a[slab_lds(u)] = la[rt][u];
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        y[rt][tt][k] = s_a[tt * BRTile::NE + BRTile::at((4 * k + ly) * 16 + lx, wave)];
+  }
+
+  acc_t acc[NRT][2];
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) acc[rt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+
+  // 2. tau tiles, PD tiles of loads in flight, staged through two LDS buffers
+  float pf[PD][4];
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (d < NTILE)
+      br_load_tau<DIAG>(pf[d], tau, br_tile_i<DIAG>(d), br_tile_j<DIAG>(d), bk, nr, r0);
+#pragma unroll
+  for (int n = 0; n < NTILE; ++n) {
+    constexpr int SB = DIAG ? 0 : 4;  // row-tile offset of block B
+    const int I = br_tile_i<DIAG>(n), J = br_tile_j<DIAG>(n);
+    float* st = s_t[n & 1];
+    br_store_tau(st, pf[n % PD]);
+    __syncthreads();
+    if (n + PD < NTILE)
+      br_load_tau<DIAG>(pf[n % PD], tau, br_tile_i<DIAG>(n + PD), br_tile_j<DIAG>(n + PD), bk,
+                        nr, r0);
+    float x[4], xt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = st[BRTile::at(lx * 16 + 4 * k + ly, wave)];
+      xt[k] = st[BRTile::at((4 * k + ly) * 16 + lx, wave)];
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      // R[A]_I += tau_IJ a[B]_J  (a[A]_J on the diagonal block)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        acc[I][tt] = Mfma<float>::run(x[k], y[SB + J][tt][k], acc[I][tt]);
+      // R[B]_J += tau_IJ^T a[A]_I  (R[A]_J off the diagonal tiles of the diagonal block)
+      if (!DIAG || I != J) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          acc[SB + J][tt] = Mfma<float>::run(xt[k], y[I][tt][k], acc[SB + J][tt]);
+      }
+    }
+  }
+
+  // 3. R -= alpha acc: every R load in flight at once, then per row tile the
+  // accumulators are staged through LDS so that the stores are coalesced
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) la[rt][u] = slab_ok(rt, u) ? R[slab_off(rt, u)] : 0.f;
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt) {
+    if ((rt & 3) * 16 >= nrow[rt >> 2]) continue;
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        s_a[tt * BRTile::NE + BRTile::at(Mfma<float>::row(lane, e) * 16 + lx, wave)] =
+            acc[rt][tt][e];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (slab_ok(rt, u)) R[slab_off(rt, u)] = la[rt][u] - alpha * s_a[slab_lds(u)];
+  }
+}
+
 // One thread per (grid point, row v): the point's sum over the chunk's rows v'
 // reads W once, coalesced along the grid; phi_v'(r) is shared by the nocc
 // workgroups of one point range and comes from L2.  Memory-bound: no reuse of
@@ -990,6 +1183,46 @@ k_k2d_rows(int64_t nr, int nocc, int nrows, int r0, const T* __restrict__ phi,
   R[(int64_t)v * nr + r] -= alpha * acc;
 }
 }  // namespace
+
+template <typename T>
+bool contract_block_rr_applies(int nb) {
+  return sizeof(T) == 4 && nb % 16 == 0;
+}
+
+template <typename T>
+void launch_contract_block_rr(const Geometry& g, int nb, int nocc, const T* at, const T* tau,
+                              int A0, int nA, int B0, int nB, bool diag, T alpha, T* R,
+                              hipStream_t s) {
+  if constexpr (sizeof(T) != 4) {
+    throw StatusError{WTD_ERR_SHAPE, "interleaved block contraction is FP32 only"};
+  } else {
+    WTD_REQUIRE(nA <= 64 && nB <= 64 && nA >= 1 && nB >= 1 && A0 >= 0 && B0 >= 0 &&
+                    A0 + nA <= nocc && B0 + nB <= nocc,
+                WTD_ERR_SHAPE, "row blocks of the exchange contraction must be <= 64 rows");
+    const int64_t ntile64 = (g.nr + BRTile::TP - 1) / BRTile::TP;
+    WTD_REQUIRE(ntile64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
+    const int ntile = (int)ntile64;
+    const int per = (ntile + 7) / 8;
+    dim3 grid(8 * per, (nb + 31) / 32);
+    BArgs bk{A0, nA, B0, nB, diag ? 1 : 0};
+    if (diag)
+      hipLaunchKernelGGL(k_contract_block_rr<true>, grid, dim3(BRTile::THREADS), 0, s, nb, nocc,
+                         g.nr, ntile, at, tau, bk, alpha, R);
+    else
+      hipLaunchKernelGGL(k_contract_block_rr<false>, grid, dim3(BRTile::THREADS), 0, s, nb, nocc,
+                         g.nr, ntile, at, tau, bk, alpha, R);
+    WTD_HIP(hipGetLastError());
+  }
+}
+
+template bool contract_block_rr_applies<float>(int);
+template bool contract_block_rr_applies<double>(int);
+template void launch_contract_block_rr<float>(const Geometry&, int, int, const float*,
+                                              const float*, int, int, int, int, bool, float,
+                                              float*, hipStream_t);
+template void launch_contract_block_rr<double>(const Geometry&, int, int, const double*,
+                                               const double*, int, int, int, int, bool, double,
+                                               double*, hipStream_t);
 
 template <typename T>
 void launch_k2d_rows(const Geometry& g, int nocc, int nrows, int r0, const T* phi, const T* W,

@@ -119,6 +119,15 @@ template <typename T>
 void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, const T* tau, int A0,
                            int nA, int B0, int nB, bool diag, T alpha, T* R, hipStream_t s);
 
+// The same with tau in the kTauIl-interleaved layout (FP32, nb a multiple of 16):
+// one pass over the block's tau for 32 trials at a time.
+template <typename T>
+bool contract_block_rr_applies(int nb);
+template <typename T>
+void launch_contract_block_rr(const Geometry& g, int nb, int nocc, const T* at, const T* tau,
+                              int A0, int nA, int B0, int nB, bool diag, T alpha, T* R,
+                              hipStream_t s);
+
 // K2d contraction of one trial (wtd_contract.hip): for rows v' in [r0, r0 + nrows),
 // R[v] -= alpha sum_v' phi_v' W[(v' - r0) nocc + v], W the Poisson-solved products
 // a_v' phi_v stored [pair][N_r].

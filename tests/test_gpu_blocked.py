@@ -53,6 +53,24 @@ def test_forced_blocks_fp32(systems, monkeypatch):
     assert err <= 2e-5
 
 
+@pytest.mark.parametrize("rb,nb", [("16", 16), ("48", 16), ("64", 32), ("32", 48)])
+def test_forced_blocks_fp32_interleaved(systems, monkeypatch, rb, nb):
+    """FP32 with whole 16-trial tiles: interleaved pair potentials and the
+    register-operand block contraction (32 trials per pass; Nb = 48 takes a
+    second, half-empty pass), blocks of 16 to 64 rows with a ragged last block
+    (128 = 48 + 48 + 32), compared element by element with the oracle."""
+    monkeypatch.setenv("WTD_ROW_BLOCK", rb)
+    s = systems("p5")
+    a = trials_random(s, nb)
+    say(f"blocked apply fp32 p5 row_block={rb} nb={nb}")
+    L = _ctx(s, nb, "fp32")
+    got = to_complex(L.apply(a))
+    L.close()
+    err = rel_err(got, oracle.apply_liouville(s, a))
+    say(f"  rel err {err:.3e}")
+    assert err <= 2e-5
+
+
 @pytest.mark.parametrize("term", ["K1D", "ALL"])
 def test_nocc_144_fp64(systems, term):
     """Nocc = 144 takes the blocked path by itself (blocks of 64, 64, 16 rows)."""
