@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK = 157.3  # TFLOP/s, dense FP32 matrix cores
 MEV = 3.674932e-5  # Hartree per meV
 METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at ΔE≤1 meV"
 
@@ -33,43 +34,43 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 868.3e6,
+        "bytes": 869.0e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
                 "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
-                "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
+                "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1300.3e6,
+        "bytes": 1294.5e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
                 "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
-                "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
+                "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
         },
     },
     "pair_plane_inv": {
-        "bytes": 1988.7e6,
+        "bytes": 1988.6e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
                 "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
-                "331419c69a433f3a35d80cc24c445f663752840e58df12c38f40c667c52f72a1",
+                "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
         },
     },
     "contract": {
-        "bytes": 19678.3e6,
+        "bytes": 19670.2e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "cd044aac443429e09c6706a53d41b8929f6bb010a148502bbf988dd741f5cb8a",
+                "3ccdcda5792fdce57f0e62011cee5920f2f91ca594426c248335ce36024c60bb",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
         },
@@ -299,11 +300,11 @@ def accuracy_fp32(s, nb, nroots):
             "reference": "oracle FP64 block Davidson, tests/golden/roots_c2.json"}
 
 
-def cpu_baseline(s, nb, a_np, rows=(0, 1, 2)):
+def cpu_baseline(s, nb, a_np, rows=tuple(range(8))):
     """Time the oracle on a bounded sample of the same block and extrapolate per row.
 
     A one-trial, one-row call first warms the FFT plans and the allocator; then
-    the same block is applied for output row 0 and for rows 0..2, and the block
+    the same block is applied for output row 0 and for rows 0..7, and the block
     time is the fixed part plus Nocc times the per-row part."""
     import oracle
     import oracle.planewave as pw
@@ -406,8 +407,21 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                 "algorithmic_bytes_per_launch": ab[dom], "mean_launch_ms": dom_ms}
+    # every single-kernel stage of the byte model, and the projector GEMMs of
+    # project_in (S = Phi_c^T a, a~ = Phi_c S: 2 x 2 M N K flops) on the matrix cores
+    stage_roofline = {k: {"achieved_GBps": ab[k] / (st[k][0] / st[k][1] * 1e-3) / 1e9,
+                          "frac": ab[k] / (st[k][0] / st[k][1] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "traffic": measured_traffic(k)}
+                      for k in ab if k in st}
+    gemm_flop = 2 * 2 * (nb * s.nocc) * s.ncond * (2 * s.npw)
+    gemm_ms = st["project_in"][0] / st["project_in"][1] if "project_in" in st else None
+    gemm_mfma = ({"stage": "project_in", "flop": gemm_flop, "ms": gemm_ms,
+                  "achieved_TFLOPs": gemm_flop / (gemm_ms * 1e-3) / 1e12, "peak": MFMA_FP32_PEAK,
+                  "frac": gemm_flop / (gemm_ms * 1e-3) / 1e12 / MFMA_FP32_PEAK}
+                 if gemm_ms else None)
     if s.nocc > 128 or cfg.name != "c2":
         roofline = None
+        stage_roofline = None
 
     full = None
     if args.full_steps > 0 and s.nocc <= 128:
@@ -445,6 +459,8 @@ def main():
         "fp32_over_fp64": (res["fp64"]["ms"] / fp32["ms"]) if "fp64" in res else None,
         "accuracy": acc,
         "roofline": roofline,
+        "stage_roofline": stage_roofline,
+        "gemm_mfma": gemm_mfma,
         "cpu_baseline": cpu,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
     }
