@@ -26,6 +26,7 @@ namespace {
 constexpr int kStickThreads = 256;
 constexpr int kPlaneThreads = 512;
 constexpr int kPairItems = 4;  // (plane, pack) items per workgroup of the prefetching pair kernel
+constexpr int kStickRegs = 6;  // rounds of density-stick loads held in registers by the plane kernels
 
 // items per workgroup of the pair-product kernel: kPairItems for FP64 planes up
 // to 72 x 72 (compile-time plans), one otherwise
@@ -398,15 +399,59 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
     const T* fb = q.y >= 0 ? src + (int64_t)q.y * nr + poff : nullptr;
     const T* fc = q.z >= 0 ? src + (int64_t)q.z * nr + poff : nullptr;
     const T* fd = q.w >= 0 ? src + (int64_t)q.w * nr + poff : nullptr;
-    for (int i = threadIdx.x; i < plane; i += blockDim.x) {
-      T re = fb ? fa[i] * fb[i] : fa[i];
-      T im = fc ? (fd ? fc[i] * fd[i] : fc[i]) : T(0);
-      pl[i] = {re, im};
-    }
-    __syncthreads();
-    plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
     cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nds;
-    for (int s = threadIdx.x; s < nd; s += blockDim.x) o[s] = pl[k12[s]];
+    if constexpr (SN > 0) {
+      // every load of the item is issued before any is used (the density-stick
+      // positions of the first kStickRegs rounds, then the four orbital planes),
+      // so the item waits for one round trip instead of one per plane row
+      constexpr int PL = SN * SN;
+      constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
+      int kp[kStickRegs];
+#pragma unroll
+      for (int e = 0; e < kStickRegs; ++e) {
+        const int st = threadIdx.x + e * kPlaneThreads;
+        kp[e] = st < nd ? k12[st] : -1;
+      }
+      // in two batches of plane rows, so the loads in flight fit the register
+      // budget of three workgroups per CU
+      constexpr int LB = (EL + 1) / 2;
+#pragma unroll
+      for (int e0 = 0; e0 < EL; e0 += LB) {
+        T ra[LB], rb[LB], rc[LB], rd[LB];
+#pragma unroll
+        for (int e = 0; e < LB; ++e) {
+          const int i = threadIdx.x + (e0 + e) * kPlaneThreads;
+          if (e0 + e < EL && (PL % kPlaneThreads == 0 || i < PL)) {
+            ra[e] = fa[i];
+            rb[e] = fb ? fb[i] : T(1);
+            rc[e] = fc ? fc[i] : T(0);
+            rd[e] = fd ? fd[i] : T(1);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < LB; ++e) {
+          const int i = threadIdx.x + (e0 + e) * kPlaneThreads;
+          if (e0 + e < EL && (PL % kPlaneThreads == 0 || i < PL))
+            pl[i] = {ra[e] * rb[e], rc[e] * rd[e]};
+        }
+      }
+      __syncthreads();
+      plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+#pragma unroll
+      for (int e = 0; e < kStickRegs; ++e)
+        if (kp[e] >= 0) o[threadIdx.x + e * kPlaneThreads] = pl[kp[e]];
+      for (int st = threadIdx.x + kStickRegs * kPlaneThreads; st < nd; st += blockDim.x)
+        o[st] = pl[k12[st]];
+    } else {
+      for (int i = threadIdx.x; i < plane; i += blockDim.x) {
+        T re = fb ? fa[i] * fb[i] : fa[i];
+        T im = fc ? (fd ? fc[i] * fd[i] : fc[i]) : T(0);
+        pl[i] = {re, im};
+      }
+      __syncthreads();
+      plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+      for (int st = threadIdx.x; st < nd; st += blockDim.x) o[st] = pl[k12[st]];
+    }
   }
 }
 
@@ -511,10 +556,28 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
   const int i0 = item / npack;
   const int pack = item - i0 * npack;
   const int64_t nr = (int64_t)n0 * plane;
+  const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+  // FP32 on compile-time planes: the first kStickRegs rounds of stick loads are
+  // issued before the plane is cleared
+  constexpr int KR = (SN > 0 && sizeof(T) == 4) ? kStickRegs : 0;
+  int kp[KR > 0 ? KR : 1];
+  cplx<T> sv[KR > 0 ? KR : 1];
+#pragma unroll
+  for (int e = 0; e < KR; ++e) {
+    const int st = threadIdx.x + e * kPlaneThreads;
+    kp[e] = -1;
+    if (st < nd) {
+      kp[e] = k12[st];
+      sv[e] = src[st];
+    }
+  }
   for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
   __syncthreads();
-  const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
-  for (int s = threadIdx.x; s < nd; s += blockDim.x) pl[k12[s]] = src[s];
+#pragma unroll
+  for (int e = 0; e < KR; ++e)
+    if (kp[e] >= 0) pl[kp[e]] = sv[e];
+  for (int st = threadIdx.x + KR * kPlaneThreads; st < nd; st += blockDim.x)
+    pl[k12[st]] = src[st];
   __syncthreads();
   plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
   const bool has2 = 2 * pack + 1 < nfield;
