@@ -616,8 +616,8 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
     launch_response_rows<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->vh, (const T*)c->drho,
                             (const T*)c->fxc, (T)ck, k1e, (T*)c->R, s);
     if (k1d) {
-      // FP32 with whole 16-trial tiles: pair potentials in the interleaved layout
-      // and the register-operand block contraction
+      // FP32: pair potentials in the interleaved layout and the register-operand
+      // block contraction
       const bool bil = contract_block_rr_applies<T>(nb);
       int max_npack = 0;
       for (const auto& bp : c->bpairs) max_npack = std::max(max_npack, bp.npack);

@@ -1186,7 +1186,7 @@ k_k2d_rows(int64_t nr, int nocc, int nrows, int r0, const T* __restrict__ phi,
 
 template <typename T>
 bool contract_block_rr_applies(int nb) {
-  return sizeof(T) == 4 && nb % 16 == 0;
+  return sizeof(T) == 4 && nb >= 1;
 }
 
 template <typename T>

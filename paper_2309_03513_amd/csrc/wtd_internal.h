@@ -119,8 +119,8 @@ template <typename T>
 void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, const T* tau, int A0,
                            int nA, int B0, int nB, bool diag, T alpha, T* R, hipStream_t s);
 
-// The same with tau in the kTauIl-interleaved layout (FP32, nb a multiple of 16):
-// one pass over the block's tau for 32 trials at a time.
+// The same with tau in the kTauIl-interleaved layout (FP32): one pass over the
+// block's tau for 32 trials at a time (trials past nb are zero).
 template <typename T>
 bool contract_block_rr_applies(int nb);
 template <typename T>

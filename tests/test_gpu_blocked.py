@@ -53,12 +53,13 @@ def test_forced_blocks_fp32(systems, monkeypatch):
     assert err <= 2e-5
 
 
-@pytest.mark.parametrize("rb,nb", [("16", 16), ("48", 16), ("64", 32), ("32", 48)])
+@pytest.mark.parametrize("rb,nb", [("16", 16), ("48", 16), ("64", 32), ("32", 48), ("48", 11)])
 def test_forced_blocks_fp32_interleaved(systems, monkeypatch, rb, nb):
-    """FP32 with whole 16-trial tiles: interleaved pair potentials and the
+    """FP32 row-blocked exchange: interleaved pair potentials and the
     register-operand block contraction (32 trials per pass; Nb = 48 takes a
-    second, half-empty pass), blocks of 16 to 64 rows with a ragged last block
-    (128 = 48 + 48 + 32), compared element by element with the oracle."""
+    second, half-empty pass, Nb = 11 one pass with 21 empty trials), blocks of
+    16 to 64 rows with a ragged last block (128 = 48 + 48 + 32), compared
+    element by element with the oracle."""
     monkeypatch.setenv("WTD_ROW_BLOCK", rb)
     s = systems("p5")
     a = trials_random(s, nb)
