@@ -438,8 +438,12 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->npairs = nocc * (nocc + 1) / 2;
   c->npack_pairs = (c->npairs + 1) / 2;
   // Above 128 occupied orbitals the pair triangle is processed in blocks of 64
-  // rows (WTD_ROW_BLOCK = 16, 32, 48 or 64 selects blocking for any Nocc).
-  c->row_block = nocc > 128 ? 64 : 0;
+  // rows; so is every FP32 system the all-pairs round-robin contraction does
+  // not cover (Nocc != 128 or blocks not of whole 16-trial tiles), whose
+  // register-operand block contraction is the faster one there
+  // (WTD_ROW_BLOCK = 16, 32, 48 or 64 selects blocking for any Nocc).
+  const bool rr = c->prec == WTD_FP32 && nocc == 128 && mnb % 16 == 0 && nr % 8 == 0;
+  c->row_block = (nocc > 128 || (c->prec == WTD_FP32 && !rr)) ? 64 : 0;
   if (const char* e = std::getenv("WTD_ROW_BLOCK")) {
     const int rb = std::atoi(e);
     WTD_REQUIRE(rb >= 0 && rb <= 64 && rb % 16 == 0, WTD_ERR_ARG,
@@ -623,8 +627,11 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
       for (const auto& bp : c->bpairs) max_npack = std::max(max_npack, bp.npack);
       WTD_REQUIRE(!bil || c->pair_chunk % 2 == 0 || c->pair_chunk >= max_npack, WTD_ERR_SHAPE,
                   "pair chunk must start on whole groups of 4 pairs");
+      // one block pair holds every pair: its potentials can be kept between applies
+      const bool single = c->bpairs.size() == 1;
+      const bool reuse = single && c->tau_cache && c->tau_valid;
       for (const auto& bp : c->bpairs) {
-        for (int p0 = 0; p0 < bp.npack; p0 += c->pair_chunk) {
+        for (int p0 = 0; p0 < (reuse ? 0 : bp.npack); p0 += c->pair_chunk) {
           const int np = std::min(c->pair_chunk, bp.npack - p0);
           const int nf = std::min(2 * np, bp.npairs - 2 * p0);
           prof_next(c, 3);
@@ -636,6 +643,7 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
           launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
                                       (T*)c->tau + (int64_t)2 * p0 * g.nr, s, bil);
         }
+        if (single) c->tau_valid = c->tau_cache;
         prof_next(c, 6);
         if (bil)
           launch_contract_block_rr<T>(g, nb, nocc, (const T*)c->at, (const T*)c->tau, bp.A0,
@@ -1013,7 +1021,7 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
       if (!saved) c->tau_valid = false;
     }
   } keep{c, c->tau_cache};
-  if (!c->row_block) c->tau_cache = true;
+  if (!c->row_block || c->bpairs.size() == 1) c->tau_cache = true;
   double* V = w.alloc((size_t)max_sub * n);
   double* W = w.alloc((size_t)max_sub * n);
   double* H = w.alloc((size_t)max_sub * max_sub);
@@ -1166,7 +1174,7 @@ wtd_status zvector_impl(wtd_ctx* c, int nrhs, const double* U, double tol, int m
       if (!saved) c->tau_valid = false;
     }
   } keep{c, c->tau_cache};
-  if (!c->row_block) c->tau_cache = true;
+  if (!c->row_block || c->bpairs.size() == 1) c->tau_cache = true;
   double* zt = w.alloc((size_t)nrhs * n);
   double* r = w.alloc((size_t)nrhs * n);
   double* p = w.alloc((size_t)nrhs * n);
@@ -1346,7 +1354,7 @@ wtd_status wtd_set_occ(wtd_ctx* ctx, const double* c_occ) {
 wtd_status wtd_cache_pairs(wtd_ctx* ctx, int32_t on) {
   return guarded([&]() -> wtd_status {
     WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
-    WTD_REQUIRE(!on || ctx->row_block == 0, WTD_ERR_SHAPE,
+    WTD_REQUIRE(!on || ctx->row_block == 0 || ctx->bpairs.size() == 1, WTD_ERR_SHAPE,
                 "the row-blocked exchange keeps the pair potentials of one block pair only");
     ctx->tau_cache = on != 0;
     ctx->tau_valid = false;

@@ -22,7 +22,7 @@ def _same(x, y):
     return torch.equal(x, y)
 
 
-@pytest.mark.parametrize("cfg,prec", [("c1", "fp64"), ("p5", "fp64"), ("p5", "fp32")])
+@pytest.mark.parametrize("cfg,prec", [("c1", "fp64"), ("p5", "fp64"), ("p5", "fp32"), ("p1", "fp32")])
 def test_cached_pairs_match_recomputed(systems, cfg, prec):
     s = systems(cfg)
     nb = s.cfg.nb
