@@ -34,10 +34,10 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 869.0e6,
+        "bytes": 875.9e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
+                "fda5ba01d760e5be05c7d0d70795e1ba3152c4f0f3d306b406b8da6601ea6607",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -45,10 +45,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1294.5e6,
+        "bytes": 1295.2e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
+                "fda5ba01d760e5be05c7d0d70795e1ba3152c4f0f3d306b406b8da6601ea6607",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -56,10 +56,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_plane_inv": {
-        "bytes": 1988.6e6,
+        "bytes": 1983.4e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "85006800c9eff9a3f8b477d2f383dfae1d698309e1bf2946d60cea3b0517e1a0",
+                "fda5ba01d760e5be05c7d0d70795e1ba3152c4f0f3d306b406b8da6601ea6607",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -67,10 +67,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "contract": {
-        "bytes": 19670.2e6,
+        "bytes": 19694.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "3ccdcda5792fdce57f0e62011cee5920f2f91ca594426c248335ce36024c60bb",
+                "9288d989e1fa3fe9eeda4e7b437a3986787e22e09b88ceaa967df5d8b2b2e661",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
         },

@@ -557,19 +557,17 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
   const int pack = item - i0 * npack;
   const int64_t nr = (int64_t)n0 * plane;
   const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
-  // FP32 on compile-time planes: the first kStickRegs rounds of stick loads are
-  // issued before the plane is cleared
-  constexpr int KR = (SN > 0 && sizeof(T) == 4) ? kStickRegs : 0;
+  // compile-time planes: the first kStickRegs rounds of stick loads are issued
+  // before the plane is cleared
+  constexpr int KR = (SN > 0) ? kStickRegs : 0;
   int kp[KR > 0 ? KR : 1];
   cplx<T> sv[KR > 0 ? KR : 1];
 #pragma unroll
   for (int e = 0; e < KR; ++e) {
     const int st = threadIdx.x + e * kPlaneThreads;
-    kp[e] = -1;
-    if (st < nd) {
-      kp[e] = k12[st];
-      sv[e] = src[st];
-    }
+    const bool in = st < nd;
+    kp[e] = in ? k12[st] : -1;
+    sv[e] = in ? src[st] : cplx<T>{T(0), T(0)};
   }
   for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
   __syncthreads();
