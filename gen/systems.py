@@ -84,6 +84,12 @@ CONFIGS = {
     # contraction at a size the oracle applies in seconds)
     "p5": Config("p5", *_cubic(10.0, 24), ecut_ry=12.0, nocc=128, ncond=16, gap=0.15,
                  nb=16, nroots=4, seed=15),
+    # grids of the heterogeneous batch outside the compile-time FFT plans
+    # (96 = 2^5 3, 60 = 2^2 3 5) at its spacing and cutoff, few orbitals
+    "p6": Config("p6", *_cubic(18.0, 96), ecut_ry=40.0, nocc=20, ncond=12, gap=0.15,
+                 nb=4, nroots=2, seed=16),
+    "p7": Config("p7", *_cubic(11.25, 60), ecut_ry=40.0, nocc=34, ncond=10, gap=0.15,
+                 nb=3, nroots=2, seed=17),
     # more than 128 occupied orbitals (row-blocked exchange: blocks 64, 64, 16)
     "p4": Config("p4", *_cubic(12.0, 36), ecut_ry=20.0, nocc=144, ncond=24, gap=0.15,
                  nb=3, nroots=3, seed=14),

@@ -69,6 +69,41 @@ def test_apply_nocc128_nb16(systems, prec, tol):
         assert err <= tol
 
 
+@pytest.mark.parametrize("cfg,prec,tol,ck", [("p6", "fp32", 2e-5, None),
+                                             ("p6", "fp64", 1e-10, 0.0),
+                                             ("p7", "fp64", 1e-10, None),
+                                             ("p7", "fp32", 2e-5, None)])
+def test_apply_batch_grids(systems, cfg, prec, tol, ck):
+    """The 96^3 and 60^3 grids of the heterogeneous batch (runtime FFT plans,
+    a radix-5 factor), sampled output rows against the oracle.  FP64 on 96^3
+    runs the spin-flip operator (c_K = 0): the density response does not fit
+    there (next test)."""
+    s = systems(cfg) if ck is None else systems(cfg, c_k=ck)
+    nb = s.cfg.nb
+    a = trials_random(s, nb)
+    rows = [0, s.nocc // 2, s.nocc - 1]
+    say(f"apply {prec} cfg={cfg} grid={s.n} rows={rows}")
+    L = _ctx(s, nb, prec)
+    got = to_complex(L.apply(a))[:, rows]
+    L.close()
+    ref = oracle.apply_liouville(s, a, rows=rows)
+    err = rel_err(got, ref)
+    say(f"  rel err {err:.3e}")
+    assert err <= tol
+
+
+def test_fp64_96_response_does_not_fit_lds(systems):
+    """A 96 x 96 FP64 plane and its density accumulator (221 KB) exceed the
+    160 KB of LDS: context creation with the response term reports
+    WTD_ERR_SHAPE instead of failing at the first apply."""
+    from paper_2309_03513_amd import WtdError
+    s = systems("p6")
+    say("p6 fp64 context creation with the response term (expected shape error)")
+    with pytest.raises(WtdError) as e:
+        _ctx(s, 1, "fp64")
+    assert e.value.status == -2
+
+
 @pytest.mark.parametrize("cfg", ["c1", "p1", "p3"])
 def test_apply_fp32(systems, cfg):
     s = systems(cfg)
