@@ -704,7 +704,32 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
     int rows = (int)std::min<size_t>((size_t)nocc, c->tau_fields / (size_t)nocc);
     if (rows < nocc && (nocc & 1)) rows &= ~1;  // chunks start on whole packs
     WTD_REQUIRE(rows >= 1, WTD_ERR_SHAPE, "pair buffer too small for one row of K2d pairs");
-    for (int b = 0; b < nb; ++b) {
+    // 72 x 72 planes and even Nocc: the Poisson-solved products of as many
+    // rows as the pair buffer holds as density sticks are formed first, then
+    // transformed back and contracted by one fused kernel (no W fields)
+    const size_t cap_packs = c->tau_fields * (size_t)g.nr / 2 / ((size_t)g.n0 * g.nds);
+    const int hp = nocc / 2;
+    const int rows_f = k2d_inverse_applies(g, nocc) ? (int)std::min<size_t>(nocc, cap_packs / hp) : 0;
+    const bool fused = rows_f >= 1;
+    for (int b = 0; fused && b < nb; ++b) {
+      const int4* kq = c->k2quads + (size_t)b * c->k2_npk;
+      for (int r0 = 0; r0 < nocc; r0 += rows_f) {
+        const int nrw = std::min(rows_f, nocc - r0);
+        const int npk = nrw * hp;
+        const int k0 = r0 * hp;
+        cplx<T>* sticks = (cplx<T>*)c->tau;
+        for (int p0 = 0; p0 < npk; p0 += c->pair_chunk) {
+          const int np = std::min(c->pair_chunk, npk - p0);
+          cplx<T>* d = sticks + (int64_t)p0 * g.n0 * g.nds;
+          launch_pairs_to_dsticks<T>(g, (const T*)c->phi, kq + k0 + p0, np, nfield_all, d, s);
+          launch_dstick_poisson<T>(g, d, np, s);
+        }
+        WTD_REQUIRE(launch_k2d_inverse<T>(g, sticks, nrw, r0, nocc, (const T*)c->phi,
+                                          (T)c->alpha, (T*)c->R + (int64_t)b * nocc * g.nr, s),
+                    WTD_ERR_SHAPE, "fused K2d pass not applicable");
+      }
+    }
+    for (int b = 0; !fused && b < nb; ++b) {
       const int4* kq = c->k2quads + (size_t)b * c->k2_npk;
       for (int r0 = 0; r0 < nocc; r0 += rows) {
         const int nrw = std::min(rows, nocc - r0);

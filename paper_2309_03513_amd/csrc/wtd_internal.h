@@ -86,6 +86,14 @@ static_assert((1 << kTauIlShift) == kTauIl, "interleave factor is a power of two
 template <typename T>
 void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, int nfield,
                               T* out, hipStream_t s, bool il = false);
+// K2d inverse pass fused with its contraction (72 x 72 planes, even Nocc):
+// dst holds packs p = j (nocc / 2) + k for rows j < nrows of the chunk starting
+// at row r0; R (one trial) -= alpha sum_v' phi_v' W_v'v.  Returns false where it
+// does not apply (the caller then writes W and runs launch_k2d_rows).
+bool k2d_inverse_applies(const Geometry& g, int nocc);
+template <typename T>
+bool launch_k2d_inverse(const Geometry& g, const cplx<T>* dst, int nrows, int r0, int nocc,
+                        const T* phi, T alpha, T* R, hipStream_t s);
 template <typename T>
 void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int per_trial,
                               int nfield_per_trial, cplx<T>* wst, hipStream_t s);

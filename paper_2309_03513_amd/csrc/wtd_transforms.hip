@@ -601,6 +601,96 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
   }
 }
 
+// ---------------------------------------------------------------- K2d: inverse pass + contraction
+// Pack p = j (nocc / 2) + k of dst holds the Poisson-solved products a_bv' phi_v
+// and a_bv' phi_v+1 (v' = r0 + j, v = 2k) on density sticks.  The workgroup of
+// item (plane i0, k) transforms the packs of every row j back to the plane and
+// sums phi_v'(r) W_v'v(r) for v and v + 1 in registers, then applies
+// R_bv -= alpha sum once per plane (no W fields in HBM).
+template <int MB1, int MB2, int SN, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_k2d_inverse(const cplx<T>* __restrict__ dst, int nrows, int r0, int nocc, int n0, int n1,
+              int n2, int nd, int nds, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+              const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+              const T* __restrict__ phi, T alpha, T* __restrict__ R) {
+  if constexpr (SN == 72) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int PL = SN * SN;
+    constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
+    constexpr int KR = kStickRegs;
+    cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* twl = pl + PL;
+    const int hp = nocc / 2;
+    const int item = xcd_item(n0 * hp);
+    if (item < 0) return;
+    stage_twiddles<SN>(twl, tw1);
+    const int i0 = item / hp;
+    const int k = item - i0 * hp;
+    const int64_t nr = (int64_t)n0 * PL;
+    const int64_t poff = (int64_t)i0 * PL;
+    // stick positions are the same for every pack: taken once
+    int kp[KR];
+#pragma unroll
+    for (int e = 0; e < KR; ++e) {
+      const int st = threadIdx.x + e * kPlaneThreads;
+      kp[e] = st < nd ? k12[st] : -1;
+    }
+    cplx<T> sv[KR];
+    auto load_sticks = [&](int j) {
+      const cplx<T>* src = dst + ((int64_t)(j * hp + k) * n0 + i0) * nds;
+#pragma unroll
+      for (int e = 0; e < KR; ++e)
+        sv[e] = kp[e] >= 0 ? src[threadIdx.x + e * kPlaneThreads] : cplx<T>{T(0), T(0)};
+    };
+    T acc1[EL], acc2[EL];
+#pragma unroll
+    for (int e = 0; e < EL; ++e) acc1[e] = acc2[e] = T(0);
+    load_sticks(0);
+    for (int j = 0; j < nrows; ++j) {
+      for (int i = threadIdx.x; i < PL; i += kPlaneThreads) pl[i] = {T(0), T(0)};
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < KR; ++e)
+        if (kp[e] >= 0) pl[kp[e]] = sv[e];
+      {
+        const cplx<T>* src = dst + ((int64_t)(j * hp + k) * n0 + i0) * nds;
+        for (int st = threadIdx.x + KR * kPlaneThreads; st < nd; st += kPlaneThreads)
+          pl[k12[st]] = src[st];
+      }
+      __syncthreads();
+      if (j + 1 < nrows) load_sticks(j + 1);
+      T f[EL];
+      const T* ph = phi + (int64_t)(r0 + j) * nr + poff;
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        f[e] = (PL % kPlaneThreads == 0 || i < PL) ? ph[i] : T(0);
+      }
+      plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) {
+          const cplx<T> z = pl[i];
+          acc1[e] += f[e] * z.x;
+          acc2[e] += f[e] * z.y;
+        }
+      }
+      __syncthreads();
+    }
+    T* o1 = R + (int64_t)(2 * k) * nr + poff;
+    T* o2 = o1 + nr;
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+      const int i = threadIdx.x + e * kPlaneThreads;
+      if (PL % kPlaneThreads == 0 || i < PL) {
+        o1[i] -= alpha * acc1[e];
+        o2[i] -= alpha * acc2[e];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- real fields -> wave sticks
 // Items (plane i0, pack) in XCD-contiguous ranges, `items` consecutive items per
 // workgroup; on 72 x 72 planes the next item's two fields are loaded into
@@ -1012,6 +1102,25 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
                    static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2), out);
 }
 
+bool k2d_inverse_applies(const Geometry& g, int nocc) {
+  // 72 x 72 planes: the accumulators of a 108 x 108 plane would not fit in registers
+  return plane_static(g) == 72 && nocc % 2 == 0;
+}
+
+template <typename T>
+bool launch_k2d_inverse(const Geometry& g, const cplx<T>* dst, int nrows, int r0, int nocc,
+                        const T* phi, T alpha, T* R, hipStream_t s) {
+  if (!k2d_inverse_applies(g, nocc)) return false;
+  WTD_REQUIRE(nrows >= 1 && r0 >= 0 && r0 + nrows <= nocc, WTD_ERR_SHAPE,
+              "K2d row chunk out of range");
+  dim3 grid((unsigned)((g.n0 * (nocc / 2) + 7) / 8 * 8));
+  const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
+  WTD_PLANE_LAUNCH(k_k2d_inverse, T, grid, lds, s, dst, nrows, r0, nocc, g.n0, g.n1, g.n2, g.nd,
+                   g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   static_cast<const cplx<T>*>(g.tw2), phi, alpha, R);
+  return true;
+}
+
 template <typename T>
 void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int per_trial,
                               int nfield_per_trial, cplx<T>* wst, hipStream_t s) {
@@ -1109,6 +1218,8 @@ void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_fl
   template void launch_dstick_poisson<T>(const Geometry&, cplx<T>*, int, hipStream_t);         \
   template void launch_dsticks_to_fields<T>(const Geometry&, const cplx<T>*, int, int, T*,     \
                                             hipStream_t, bool);                                \
+  template bool launch_k2d_inverse<T>(const Geometry&, const cplx<T>*, int, int, int, const T*, \
+                                      T, T*, hipStream_t);                                     \
   template void launch_fields_to_wsticks<T>(const Geometry&, const T*, int, int, int,          \
                                             cplx<T>*, hipStream_t);                            \
   template void launch_wsticks_to_sphere<T>(const Geometry&, cplx<T>*, int, hipStream_t);      \

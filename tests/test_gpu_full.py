@@ -50,10 +50,12 @@ def test_tda_entry_point_ignores_k2_terms(systems):
 
 
 @pytest.mark.parametrize("cfg,prec,tol,rows", [("p3", "fp64", 1e-10, [0, 17, 35]),
+                                               ("p3", "fp32", 2e-5, [0, 17, 35]),
                                                ("p5", "fp64", 1e-10, [0, 77, 127]),
                                                ("p5", "fp32", 2e-5, [0, 77, 127])])
 def test_full_operator_sampled_rows(systems, cfg, prec, tol, rows):
-    """72^3 grid with Nocc = 36; Nocc = 128 with Nb = 16 (two row chunks of K2d pairs)."""
+    """72^3 grid with Nocc = 36 (the fused K2d inverse pass and contraction);
+    Nocc = 128 with Nb = 16 (two row chunks of K2d pairs)."""
     s = systems(cfg)
     nb = s.cfg.nb
     a = trials_random(s, nb)
