@@ -96,7 +96,8 @@ def log(msg):
 
 
 def stage_bytes(s, nb, sz, nd, nw, chunk_packs):
-    """Algorithmic HBM bytes per launch of the single-kernel stages."""
+    """Algorithmic HBM bytes per launch of the single-kernel stages: each input read
+    once and each output written once."""
     nr = int(np.prod(s.n))
     n0 = s.n[0]
     nocc = s.nocc
@@ -359,8 +360,8 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design (DESIGN.md), not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "path over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
