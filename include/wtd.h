@@ -184,7 +184,8 @@ wtd_status wtd_apply_liouville_bwd(wtd_ctx *ctx, int32_t nb, const void *a, cons
 /* Block Davidson for the nroots lowest eigenpairs of L (Sec. 4; normalisation
  * sum_v <x_v|x_v> = 1 of Eq. ltda).  Synchronous.  Where the exchange is not
  * row-blocked the pair potentials are formed once per call and reused by every
- * apply of the run (as with wtd_cache_pairs).
+ * apply of the run (as with wtd_cache_pairs).  On a non-null stream the applies
+ * after the first are replayed from one HIP graph per block size.
  * nb: block size (nroots <= nb <= max_nb); tol: residual 2-norm per root;
  * max_sub: basis cap before restart (<= 0: 4*nb); guess: device
  * [nb][nocc][npw][2] FP64 or NULL (lowest unit transitions).

@@ -1126,9 +1126,54 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
     return added;
   };
 
+  // The applies of the run after the first (which forms the pair potentials
+  // when they are kept) are replayed from one HIP graph per block size k,
+  // captured on fixed staging buffers: the k new basis vectors are copied in,
+  // the graph runs the whole apply, the products are copied out
+  // (WTD_DAVIDSON_GRAPHS=0 applies eagerly; so does a run with profiling on or
+  // on the null stream, which cannot be captured).
+  struct Graphs {
+    std::map<int, hipGraphExec_t> ex;
+    ~Graphs() {
+      for (auto& e : ex) (void)hipGraphExecDestroy(e.second);
+    }
+  } graphs;
+  bool use_graphs = !c->prof.on && s != nullptr;
+  if (const char* e = std::getenv("WTD_DAVIDSON_GRAPHS")) use_graphs = use_graphs && std::atoi(e) != 0;
+  double* gx = use_graphs ? w.alloc((size_t)nb * n) : nullptr;
+  double* gt = use_graphs ? w.alloc((size_t)nb * n) : nullptr;
+  int napply = 0;
+  auto apply_block = [&](int k, const double* X, double* T) {
+    if (!use_graphs || napply++ == 0) {
+      apply_transition_any(c, k, X, T, tda_mask(c));
+      return;
+    }
+    auto it = graphs.ex.find(k);
+    if (it == graphs.ex.end()) {
+      hipGraph_t gr = nullptr;
+      hipGraphExec_t ge = nullptr;
+      WTD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        apply_transition_any(c, k, gx, gt, tda_mask(c));
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      WTD_HIP(hipStreamEndCapture(s, &gr));
+      const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      WTD_HIP(ie);
+      it = graphs.ex.emplace(k, ge).first;
+    }
+    WTD_HIP(hipMemcpyAsync(gx, X, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    WTD_HIP(hipGraphLaunch(it->second, s));
+    WTD_HIP(hipMemcpyAsync(T, gt, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  };
+
   int added = orthonormalise_append(nb);
   WTD_REQUIRE(added > 0, WTD_ERR_ARG, "Davidson guess block is rank deficient");
-  apply_transition_any(c, added, V, W, tda_mask(c));
+  apply_block(added, V, W);
   m = added;
   int it = 0;
   bool converged = false;
@@ -1163,7 +1208,7 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
     }
     const int na = orthonormalise_append((int)act.size());
     if (na == 0) break;
-    apply_transition_any(c, na, V + (int64_t)m * n, W + (int64_t)m * n, tda_mask(c));
+    apply_block(na, V + (int64_t)m * n, W + (int64_t)m * n);
     m += na;
   }
   const int nr_out = std::min(nroots, kcur);
