@@ -27,6 +27,12 @@ constexpr int kStickThreads = 256;
 constexpr int kPlaneThreads = 512;
 constexpr int kPairItems = 4;  // (plane, pack) items per workgroup of the prefetching pair kernel
 constexpr int kStickRegs = 6;  // rounds of density-stick loads held in registers by the plane kernels
+// (108 x 108 planes run one workgroup per CU, so they keep every round of the
+// 108^3 density sticks in registers)
+template <int SN>
+constexpr int stick_regs() {
+  return SN == 108 ? 11 : kStickRegs;
+}
 
 // items per workgroup of the pair-product kernel: kPairItems for FP64 planes up
 // to 72 x 72 (compile-time plans), one otherwise
@@ -406,9 +412,10 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
       // so the item waits for one round trip instead of one per plane row
       constexpr int PL = SN * SN;
       constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
-      int kp[kStickRegs];
+      constexpr int KS = stick_regs<SN>();
+      int kp[KS];
 #pragma unroll
-      for (int e = 0; e < kStickRegs; ++e) {
+      for (int e = 0; e < KS; ++e) {
         const int st = threadIdx.x + e * kPlaneThreads;
         kp[e] = st < nd ? k12[st] : -1;
       }
@@ -438,9 +445,9 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
       __syncthreads();
       plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
 #pragma unroll
-      for (int e = 0; e < kStickRegs; ++e)
+      for (int e = 0; e < KS; ++e)
         if (kp[e] >= 0) o[threadIdx.x + e * kPlaneThreads] = pl[kp[e]];
-      for (int st = threadIdx.x + kStickRegs * kPlaneThreads; st < nd; st += blockDim.x)
+      for (int st = threadIdx.x + KS * kPlaneThreads; st < nd; st += blockDim.x)
         o[st] = pl[k12[st]];
     } else {
       for (int i = threadIdx.x; i < plane; i += blockDim.x) {
@@ -559,7 +566,7 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
   const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
   // compile-time planes: the first kStickRegs rounds of stick loads are issued
   // before the plane is cleared
-  constexpr int KR = (SN > 0) ? kStickRegs : 0;
+  constexpr int KR = (SN > 0) ? stick_regs<SN>() : 0;
   int kp[KR > 0 ? KR : 1];
   cplx<T> sv[KR > 0 ? KR : 1];
 #pragma unroll
