@@ -34,10 +34,10 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 877.5e6,
+        "bytes": 876.2e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "962a015a9bec0f84e18fd60c0a88c36295aa58cf6d0da890cd87aa7f62586c1c",
+                "bb3a0e5730a38a1da72b21d5bd40476d0a31e7a7ae75b9789d8fc7f72e1ebd2d",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -45,10 +45,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1295.3e6,
+        "bytes": 1296.1e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "962a015a9bec0f84e18fd60c0a88c36295aa58cf6d0da890cd87aa7f62586c1c",
+                "bb3a0e5730a38a1da72b21d5bd40476d0a31e7a7ae75b9789d8fc7f72e1ebd2d",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -56,10 +56,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_plane_inv": {
-        "bytes": 1983.3e6,
+        "bytes": 1983.4e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "962a015a9bec0f84e18fd60c0a88c36295aa58cf6d0da890cd87aa7f62586c1c",
+                "bb3a0e5730a38a1da72b21d5bd40476d0a31e7a7ae75b9789d8fc7f72e1ebd2d",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -67,7 +67,7 @@ MEASURED_TRAFFIC = {
         },
     },
     "contract": {
-        "bytes": 19698.5e6,
+        "bytes": 19672.2e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
                 "9288d989e1fa3fe9eeda4e7b437a3986787e22e09b88ceaa967df5d8b2b2e661",

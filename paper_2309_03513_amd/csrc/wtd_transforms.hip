@@ -27,6 +27,12 @@ constexpr int kStickThreads = 256;
 constexpr int kPlaneThreads = 512;
 constexpr int kPairItems = 4;  // (plane, pack) items per workgroup of the prefetching pair kernel
 constexpr int kStickRegs = 6;  // rounds of density-stick loads held in registers by the plane kernels
+// wave sticks per thread of the compile-time plane kernels (577 sticks at
+// 72^3 / 40 Ry, 1,305 at 108^3)
+template <int SN>
+constexpr int wave_stick_regs() {
+  return SN == 108 ? 3 : 2;
+}
 // (108 x 108 planes run one workgroup per CU, so they keep every round of the
 // 108^3 density sticks in registers)
 template <int SN>
@@ -197,12 +203,12 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   const int64_t poff = (int64_t)i0 * plane;
   if (drho)
     for (int i = threadIdx.x; i < plane; i += blockDim.x) acc[i] = T(0);
-  if constexpr (SN == 72) {
+  if constexpr (SN > 0) {
     // the next pack's sticks and the current pack's orbital planes are loaded
     // into registers before the plane FFT, so their latency overlaps it
     constexpr int PL = SN * SN;
     constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
-    constexpr int WS = 2;  // wave sticks per thread (nw <= WS * kPlaneThreads, host-checked)
+    constexpr int WS = wave_stick_regs<SN>();  // nw <= WS * kPlaneThreads, host-checked
     cplx<T> sv[WS];
     int kv[WS];
 #pragma unroll
@@ -700,7 +706,7 @@ k_k2d_inverse(const cplx<T>* __restrict__ dst, int nrows, int r0, int nocc, int 
 
 // ---------------------------------------------------------------- real fields -> wave sticks
 // Items (plane i0, pack) in XCD-contiguous ranges, `items` consecutive items per
-// workgroup; on 72 x 72 planes the next item's two fields are loaded into
+// workgroup; on compile-time planes the next item's two fields are loaded into
 // registers while the current plane is transformed.
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
@@ -732,7 +738,7 @@ k_fields_to_wsticks(const T* __restrict__ fields, int npt, int per_trial, int it
     cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nws;
     for (int st = threadIdx.x; st < nw; st += blockDim.x) o[st] = pl[k12[st]];
   };
-  if constexpr (SN == 72) {
+  if constexpr (SN > 0) {
     constexpr int PL = SN * SN;
     constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
     T r1[EL], r2[EL];
@@ -1056,8 +1062,9 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   const int npt = (per_trial + 1) / 2;
   if (!drho || !part) ngroup = 1;
   ngroup = std::max(1, std::min(ngroup, npt));
-  WTD_REQUIRE(plane_static(g) != 72 || g.nw <= 2 * kPlaneThreads, WTD_ERR_SHAPE,
-              "too many wave sticks for the 72 x 72 plane kernel");
+  WTD_REQUIRE((plane_static(g) != 72 || g.nw <= wave_stick_regs<72>() * kPlaneThreads) &&
+                  (plane_static(g) != 108 || g.nw <= wave_stick_regs<108>() * kPlaneThreads),
+              WTD_ERR_SHAPE, "too many wave sticks for the compile-time plane kernel");
   dim3 grid((unsigned)((g.n0 * nb * ngroup + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
   T* dtarget = (ngroup > 1) ? part : drho;
@@ -1134,7 +1141,7 @@ void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int pe
   (void)nfield_per_trial;
   const int npt = (per_trial + 1) / 2;
   const int npack = nb * npt;
-  const int items = plane_static(g) == 72 ? kPairItems : 1;
+  const int items = plane_static(g) > 0 ? kPairItems : 1;
   const int ngrp = (g.n0 * npack + items - 1) / items;
   dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
