@@ -18,7 +18,7 @@ def _ctx(s, nb, prec, terms=7):
 
 
 @pytest.mark.parametrize("cfg,prec,tol", [("c1", "fp64", 1e-10), ("p5", "fp64", 1e-10),
-                                          ("p5", "fp32", 2e-5)])
+                                          ("p5", "fp32", 2e-5), ("p1", "fp32", 2e-5)])
 def test_autotuned_apply_matches_oracle(systems, cfg, prec, tol):
     s = systems(cfg)
     nb = s.cfg.nb
