@@ -856,17 +856,29 @@ k_contract_block(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ 
 }
 
 // R[b][v] = c_K phi_v (v_H,b + f_xc drho_b), or 0 without the response term
+// One thread per grid point and group of kRespRows rows v: the rows' phi values
+// are read once and reused for every trial, whose potential c_K (v_H + f_xc drho)
+// is formed once per trial.
+constexpr int kRespRows = 8;
 template <typename T>
 __global__ void k_response_rows(int nb, int nocc, int64_t nr, const T* __restrict__ phi,
                                 const T* __restrict__ vh, const T* __restrict__ drho,
                                 const T* __restrict__ fxc, T ck, int k1e, T* __restrict__ R) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int bv = blockIdx.y;
+  const int v0 = blockIdx.y * kRespRows;
   if (r >= nr) return;
-  const int b = bv / nocc, v = bv - b * nocc;
-  T val = T(0);
-  if (k1e) val = ck * phi[(int64_t)v * nr + r] * (vh[(int64_t)b * nr + r] + fxc[r] * drho[(int64_t)b * nr + r]);
-  R[(int64_t)bv * nr + r] = val;
+  T ph[kRespRows];
+#pragma unroll
+  for (int j = 0; j < kRespRows; ++j)
+    ph[j] = (k1e && v0 + j < nocc) ? phi[(int64_t)(v0 + j) * nr + r] : T(0);
+  const T fx = k1e ? fxc[r] : T(0);
+  for (int b = 0; b < nb; ++b) {
+    const T u = k1e ? ck * (vh[(int64_t)b * nr + r] + fx * drho[(int64_t)b * nr + r]) : T(0);
+    T* o = R + ((int64_t)b * nocc + v0) * nr + r;
+#pragma unroll
+    for (int j = 0; j < kRespRows; ++j)
+      if (v0 + j < nocc) o[(int64_t)j * nr] = ph[j] * u;
+  }
 }
 
 }  // namespace
@@ -948,7 +960,7 @@ namespace wtd {
 template <typename T>
 void launch_response_rows(const Geometry& g, int nb, int nocc, const T* phi, const T* vh,
                           const T* drho, const T* fxc, T ck, bool k1e, T* R, hipStream_t s) {
-  dim3 grid((unsigned)((g.nr + 255) / 256), (unsigned)(nb * nocc));
+  dim3 grid((unsigned)((g.nr + 255) / 256), (unsigned)((nocc + kRespRows - 1) / kRespRows));
   hipLaunchKernelGGL(k_response_rows<T>, grid, dim3(256), 0, s, nb, nocc, g.nr, phi, vh, drho, fxc,
                      ck, (int)k1e, R);
   WTD_HIP(hipGetLastError());
