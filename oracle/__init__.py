@@ -20,7 +20,7 @@ invariance of the exchange term, the alpha = 0 and c_K = 0 reductions, the
 G = 0 eigenvalue shift and dense diagonalisation.
 """
 from .planewave import (  # noqa: F401
-    gvectors, gamma_inner, real_space, coefficients, coulomb_kernel, poisson,
+    gvectors, gamma_inner, gamma_overlap, real_space, coefficients, coulomb_kernel, poisson,
 )
 from .liouville import (  # noqa: F401
     TERM_D, TERM_K1E, TERM_K1D, TERM_ALL, TERM_K2E, TERM_K2D, TERM_FULL, apply_liouville,

@@ -26,7 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 from .liouville import TERM_ALL, TERM_K1D, TERM_K1E, apply_liouville
-from .planewave import coefficients, coulomb_kernel, gamma_inner, poisson, real_space
+from .planewave import coefficients, coulomb_kernel, gamma_overlap, poisson, real_space
 
 
 def _weights(npw):
@@ -58,7 +58,7 @@ def grad_occ(s, a, g, terms=TERM_ALL, occ=None):
     if not (k1e or k1d):
         return np.zeros((nocc, npw), dtype=np.complex128)
 
-    S = gamma_inner(c_cond[None, None, :, :], a[:, :, None, :])            # [nb][nocc][nc]
+    S = gamma_overlap(a.reshape(-1, a.shape[-1]), c_cond).reshape(a.shape[0], a.shape[1], -1)
     at = real_space(np.einsum("bvc,cm->bvm", S, c_cond), mill, cell, n)
     G = np.einsum("cm,bvm->bvc", c_cond.real, g.real) + np.einsum("cm,bvm->bvc", c_cond.imag,
                                                                    g.imag)

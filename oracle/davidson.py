@@ -16,7 +16,9 @@ with a diagonal preconditioner:
 * classical Gram-Schmidt, applied twice, against V and the earlier accepted
   corrections; a correction whose norm falls below 1e-10 is dropped;
 * when the basis would exceed max_sub vectors it is collapsed to the nb
-  lowest Ritz vectors (with W collapsed alongside).
+  lowest Ritz vectors (with W collapsed alongside);
+* when every correction is dropped (the basis already holds them) the run
+  stops unconverged and reports the iteration it stopped at.
 """
 from __future__ import annotations
 
@@ -53,6 +55,7 @@ def davidson(matvec, diag, nroots, nb, tol=1e-8, max_iter=100, max_sub=None, gue
             V, _ = np.linalg.qr(V)
     W = matvec(V)
     theta = rn = X = None
+    it = 0
     for it in range(1, max_iter + 1):
         H = V.T @ W
         H = 0.5 * (H + H.T)
@@ -87,11 +90,12 @@ def davidson(matvec, diag, nroots, nb, tol=1e-8, max_iter=100, max_sub=None, gue
                 continue
             accepted.append(t / nt)
         if not accepted:
+            # every correction lies in the basis already: nothing left to add
             break
         Tn = np.column_stack(accepted)
         V = np.column_stack([V, Tn])
         W = np.column_stack([W, matvec(Tn)])
-    return theta[:nroots], X[:, :nroots], rn[:nroots], max_iter, False
+    return theta[:nroots], X[:, :nroots], rn[:nroots], it, False
 
 
 def davidson_transition(s, nroots, nb, tol=1e-8, max_iter=100, max_sub=None,

@@ -47,7 +47,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .planewave import coefficients, coulomb_kernel, gamma_inner, poisson, real_space
+from .planewave import coefficients, coulomb_kernel, gamma_overlap, poisson, real_space
 
 TERM_D = 1
 TERM_K1E = 2
@@ -81,10 +81,10 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None,
 
     # step 1: project the input onto the unoccupied manifold
     if projector == "span":
-        S = gamma_inner(c_cond[None, None, :, :], a[:, :, None, :])         # [nb][nocc][nc]
+        S = gamma_overlap(a.reshape(nb * nocc, npw), c_cond).reshape(nb, nocc, -1)  # [nb][nocc][nc]
         a_t = np.einsum("bvc,cm->bvm", S, c_cond)
     elif projector == "complement":
-        O = gamma_inner(c_occ[None, None, :, :], a[:, :, None, :])          # [nb][nocc][nocc]
+        O = gamma_overlap(a.reshape(nb * nocc, npw), c_occ).reshape(nb, nocc, nocc)
         a_t = a - np.einsum("bvu,um->bvm", O, c_occ)
     else:
         raise ValueError(projector)
@@ -144,10 +144,10 @@ def apply_liouville(s, a, terms=TERM_ALL, rows=None, projector="span", occ=None,
         orbs = np.concatenate([c_occ, c_cond])
         eps = np.concatenate([s.eps_occ, s.eps_cond])
         at_r = a_t[:, rows]
-        proj = gamma_inner(orbs[None, None], at_r[:, :, None, :])          # [nb][rows][norb]
+        proj = gamma_overlap(at_r.reshape(-1, npw), orbs).reshape(nb, len(rows), -1)
         h_at = np.einsum("bvn,n,nm->bvm", proj, eps, orbs)
         out = out + h_at - np.asarray(s.eps_occ)[rows][None, :, None] * at_r
-    O = gamma_inner(c_occ[None, None, :, :], out[:, :, None, :])
+    O = gamma_overlap(out.reshape(-1, npw), c_occ).reshape(nb, len(rows), nocc)
     return out - np.einsum("bvu,um->bvm", O, c_occ)
 
 
@@ -164,4 +164,5 @@ def apply_transition(s, X, terms=TERM_ALL):
     X = np.asarray(X, dtype=np.float64)
     a = np.einsum("bvc,cm->bvm", X, s.c_cond)
     la = apply_liouville(s, a, terms=terms)
-    return gamma_inner(s.c_cond[None, None, :, :], la[:, :, None, :])
+    nb, nocc, npw = la.shape
+    return gamma_overlap(la.reshape(nb * nocc, npw), s.c_cond).reshape(nb, nocc, -1)

@@ -40,6 +40,16 @@ def gamma_inner(f, g):
     return np.sum(w * (f.real * g.real + f.imag * g.imag), axis=-1)
 
 
+def gamma_overlap(f, g):
+    """<f_i|g_j> for every pair of half-sphere coefficient rows f [nf][npw] and
+    g [ng][npw], as one weighted matrix product (result [nf][ng])."""
+    f = np.asarray(f, dtype=np.complex128)
+    g = np.asarray(g, dtype=np.complex128)
+    w = np.full(f.shape[-1], 2.0)
+    w[0] = 1.0
+    return (f.real * w) @ g.real.T + (f.imag * w) @ g.imag.T
+
+
 def _box(c_half, mill, n):
     """Place half-sphere coefficients and their conjugates in the FFT box."""
     lead = c_half.shape[:-1]

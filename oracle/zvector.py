@@ -55,35 +55,26 @@ def cg_inexact(matvec_exact, matvec_approx, rhs, tol=1e-8, max_iter=200, lambda_
 def solve_zvector_transition(s, U, tol=1e-8, max_iter=200, lambda_thr=0.0):
     """Z-vectors for right-hand sides U [nrhs][nocc][nc] in transition coordinates.
 
-    The right-hand sides are solved side by side, one CG each, with one shared
-    operator per iteration: the approximate operator is taken from the first
-    iteration at which every unconverged residual norm is below lambda_thr (for
-    one right-hand side this is the rule of cg_inexact).  A converged system is
-    left as it is.  Returns (Z [nrhs][nocc][nc], residual norms, iterations,
-    applies of the exact operator)."""
+    Each right-hand side is its own CG solve (cg_inexact) with its own switch
+    to the approximate operator (Sec. 3.3 states the switch for one CG).
+    Returns (Z [nrhs][nocc][nc], residual norms, iterations, exact applies),
+    the last two as the maxima over the right-hand sides."""
     U = np.asarray(U, dtype=np.float64)
     nrhs, nocc, nc = U.shape
+
+    def op(terms):
+        def mv(x):
+            return apply_transition(s, x.reshape(1, nocc, nc), terms=terms).ravel()
+        return mv
+
+    exact = op(TERM_FULL)
+    approx = op(TERM_FULL & ~TERM_K2D)
     Z = np.zeros((nrhs, nocc * nc))
-    R = U.reshape(nrhs, -1).copy()
-    P = R.copy()
-    rr = np.sum(R * R, axis=1)
-    active = np.sqrt(rr) > tol
-    use_exact = True
-    n_exact = 0
-    it = 0
-    while active.any() and it < max_iter:
-        if use_exact and lambda_thr > 0.0 and np.all(np.sqrt(rr[active]) < lambda_thr):
-            use_exact = False
-        terms = TERM_FULL if use_exact else TERM_FULL & ~TERM_K2D
-        AP = apply_transition(s, P.reshape(nrhs, nocc, nc), terms=terms).reshape(nrhs, -1)
-        n_exact += int(use_exact)
-        for k in np.flatnonzero(active):
-            step = rr[k] / float(P[k] @ AP[k])
-            Z[k] += step * P[k]
-            R[k] -= step * AP[k]
-            rr_new = float(R[k] @ R[k])
-            P[k] = R[k] + (rr_new / rr[k]) * P[k]
-            rr[k] = rr_new
-        active = np.sqrt(rr) > tol
-        it += 1
-    return Z.reshape(nrhs, nocc, nc), np.sqrt(rr), it, n_exact
+    rn = np.zeros(nrhs)
+    its, nex = [], []
+    for k in range(nrhs):
+        Z[k], rn[k], it, ne = cg_inexact(exact, approx, U[k], tol=tol, max_iter=max_iter,
+                                         lambda_thr=lambda_thr)
+        its.append(it)
+        nex.append(ne)
+    return Z.reshape(nrhs, nocc, nc), rn, max(its), max(nex)

@@ -44,7 +44,7 @@ def test_grad_occ_matches_central_difference(systems, terms):
     em = oracle.energy(s, a, g, terms, occ=s.c_occ - H * dc)
     fd = (ep - em) / (2 * H)
     an = np.sum(go.real * dc.real + go.imag * dc.imag)
-    assert abs(an - fd) <= 1e-8 * max(abs(fd), 1e-12), (an, fd)
+    assert abs(an - fd) <= 1e-9 * max(abs(fd), 1e-12), (an, fd)
 
 
 def test_grad_occ_is_zero_for_d_only(systems):

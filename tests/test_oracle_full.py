@@ -128,3 +128,26 @@ def test_inexact_switch(systems):
     # the approximate phase corrects a residual of size ~thr with an operator
     # that differs by K2d: the error stays at the size of thr relative to U
     assert err <= 10 * thr / np.linalg.norm(U)
+
+
+def test_inexact_switch_is_per_system(systems):
+    """Two right-hand sides whose first residuals lie on either side of
+    lambda_thr: the small one is solved with the approximate operator from the
+    start (so it solves (L - K2d) Z = U to tol), the large one starts exact and
+    switches later (error of the size of thr), as two separate CG solves do."""
+    s = systems("c1")
+    nocc, nc = s.c_occ.shape[0], s.c_cond.shape[0]
+    Ma = _dense(s, APPROX)
+    M = _dense(s, FULL)
+    rng = np.random.default_rng(13)
+    U = rng.standard_normal((2, nocc, nc))
+    U[1] *= 1e-4
+    thr = 1e-2 * np.linalg.norm(U[0])
+    assert np.linalg.norm(U[1]) < thr < np.linalg.norm(U[0])
+    Z, res, its, nex = oracle.solve_zvector_transition(s, U, tol=1e-13, lambda_thr=thr)
+    ref_a = np.linalg.solve(Ma, U[1].ravel())
+    assert np.abs(Z[1].ravel() - ref_a).max() <= 1e-9 * np.abs(ref_a).max()
+    exact = np.linalg.solve(M, U[0].ravel())
+    err = np.linalg.norm(Z[0].ravel() - exact) / np.linalg.norm(exact)
+    assert 1e-14 < err <= 10 * thr / np.linalg.norm(U[0])
+    assert 0 < nex < its

@@ -58,6 +58,25 @@ def test_round_trip_and_gamma_inner_is_quadrature():
     assert np.abs(gi - np.eye(3)).max() < 1e-13
 
 
+def test_gamma_overlap_is_quadrature():
+    """<f_i|g_j> of two unrelated coefficient sets equals the grid quadrature
+    (Omega/N_r) sum_j f(r_j) g(r_j) of their real-space fields."""
+    s = _tiny()
+    rng = np.random.default_rng(41)
+    npw = s.mill.shape[0]
+    f = rng.standard_normal((4, npw)) + 1j * rng.standard_normal((4, npw))
+    g = rng.standard_normal((5, npw)) + 1j * rng.standard_normal((5, npw))
+    f[:, 0] = f[:, 0].real
+    g[:, 0] = g[:, 0].real
+    F = oracle.real_space(f, s.mill, s.cell, s.n).reshape(4, -1)
+    G = oracle.real_space(g, s.mill, s.cell, s.n).reshape(5, -1)
+    omega, nr = float(np.prod(s.cell)), int(np.prod(s.n))
+    quad = (omega / nr) * F @ G.T
+    ov = oracle.gamma_overlap(f, g)
+    assert ov.shape == (4, 5)
+    assert np.abs(quad - ov).max() <= 1e-12 * np.abs(quad).max()
+
+
 # ---------------------------------------------------------------- Coulomb kernel / Poisson
 @pytest.mark.parametrize("v_g0", [0.0, 0.37])
 def test_poisson_matches_realspace_coulomb_sum(v_g0):
@@ -211,3 +230,21 @@ def test_davidson_restart_path(systems):
     th, X, rn, it, ok = oracle.davidson_transition(s, nroots=3, nb=3, tol=1e-9, max_sub=6)
     assert ok
     assert np.abs(th - ev[:3]).max() <= 1e-10
+
+
+def test_davidson_exhausted_basis_reports_its_iteration():
+    """With a tolerance below rounding, the basis of a 12 x 12 problem fills up
+    after three blocks of 4; every later correction is dropped, so the run
+    stops unconverged at that iteration (not at max_iter) with the exact
+    spectrum of the matrix."""
+    rng = np.random.default_rng(31)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    ev = np.sort(rng.uniform(0.1, 2.0, 12))
+    A = (Q * ev) @ Q.T
+    A = 0.5 * (A + A.T)
+    th, X, rn, it, ok = oracle.davidson(lambda V: A @ V, np.diag(A), nroots=4, nb=4, tol=0.0,
+                                        max_iter=50)
+    assert not ok
+    assert 3 <= it <= 4
+    assert np.abs(th - ev[:4]).max() <= 1e-12
+    assert np.all(rn <= 1e-12)
