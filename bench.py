@@ -301,33 +301,52 @@ def accuracy_fp32(s, nb, nroots):
             "reference": "oracle FP64 block Davidson, tests/golden/roots_c2.json"}
 
 
-def cpu_baseline(s, nb, a_np, rows=tuple(range(8))):
-    """Time the oracle on a bounded sample of the same block and extrapolate per row.
+def cpu_baseline(s, nb, a_np, single_rows=(0, 1, 2)):
+    """Time the oracle on the same block: one whole block on every host core
+    (the value), and a single-core figure extrapolated from a row sample.
 
-    A one-trial, one-row call first warms the FFT plans and the allocator; then
-    the same block is applied for output row 0 and for rows 0..7, and the block
-    time is the fixed part plus Nocc times the per-row part."""
+    All cores: scipy.fft workers and the BLAS pool set to the affinity count;
+    a one-trial, one-row call first warms the FFT plans and the allocator, then
+    the whole Nb-trial block (every output row) is applied and timed.
+    One core: the same block for output row 0 and for rows 0..2 with one FFT
+    worker and one BLAS thread; the block time is the fixed part plus Nocc
+    times the per-row part (stated as extrapolated)."""
     import oracle
     import oracle.planewave as pw
+    from threadpoolctl import threadpool_limits
     cores = len(os.sched_getaffinity(0))
     pw._WORKERS = cores
-    oracle.apply_liouville(s, a_np[:1], rows=[rows[0]])
-    t0 = time.perf_counter()
-    oracle.apply_liouville(s, a_np, rows=[rows[0]])
-    t1 = time.perf_counter()
-    oracle.apply_liouville(s, a_np, rows=list(rows))
-    t2 = time.perf_counter()
+    with threadpool_limits(limits=cores):
+        oracle.apply_liouville(s, a_np[:1], rows=[0])
+        t0 = time.perf_counter()
+        oracle.apply_liouville(s, a_np)
+        t_block = time.perf_counter() - t0
+    log(f"oracle, {cores} cores: whole block {t_block:.1f} s")
+    rows = list(single_rows)
+    pw._WORKERS = 1
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.apply_liouville(s, a_np, rows=rows[:1])
+        t1 = time.perf_counter()
+        oracle.apply_liouville(s, a_np, rows=rows)
+        t2 = time.perf_counter()
+    pw._WORKERS = cores
     t_one, t_many = t1 - t0, t2 - t1
     t_row = max((t_many - t_one) / (len(rows) - 1), 0.0)
     t_fixed = max(t_one - t_row, 0.0)
-    t_block = t_fixed + s.nocc * t_row
-    log(f"oracle: fixed {t_fixed:.1f} s, {t_row:.2f} s/row -> {t_block:.0f} s per block")
+    t1_block = t_fixed + s.nocc * t_row
+    log(f"oracle, 1 core: fixed {t_fixed:.1f} s, {t_row:.2f} s/row -> {t1_block:.0f} s per block "
+        "(extrapolated)")
     return {"value": nb / t_block, "unit": "trial-vector applies/s", "cores": cores,
             "kind": "oracle",
-            "sample": (f"oracle apply on the same Nb={nb} block, output rows {list(rows)} and "
-                       f"{[rows[0]]} of {s.nocc} timed ({t_many + t_one:.1f} s of CPU), "
-                       f"block time = fixed {t_fixed:.1f} s + {s.nocc} x {t_row:.2f} s/row"),
-            "seconds_per_block": t_block}
+            "sample": (f"whole oracle apply of the same Nb={nb} block (all {s.nocc} output rows) "
+                       f"on {cores} host cores, measured: {t_block:.1f} s"),
+            "all_core_full_block_s": t_block,
+            "single_core": {"value": nb / t1_block, "unit": "trial-vector applies/s",
+                            "cores": 1, "seconds_per_block": t1_block, "extrapolated": True,
+                            "method": (f"same block, output rows {rows[:1]} and {rows} timed on "
+                                       f"one core ({t_one + t_many:.1f} s); block = fixed "
+                                       f"{t_fixed:.1f} s + {s.nocc} x {t_row:.2f} s/row")}}
 
 
 def main():

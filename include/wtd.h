@@ -150,15 +150,18 @@ wtd_status wtd_apply_transition(wtd_ctx *ctx, int32_t nb, const double *X, doubl
 wtd_status wtd_apply_full(wtd_ctx *ctx, int32_t nb, const void *a, void *la);
 
 /* Conjugate-gradient solve of the Z-vector equation (Eq. z-v-eq) with the
- * inexact Krylov scheme of Sec. 3.3: the full operator (as wtd_apply_full) is
- * applied until every unconverged residual norm is below lambda_thr, K2d is
- * dropped from then on (lambda_thr = 0: never).  The nrhs right-hand sides are
- * independent CG systems solved side by side, one block apply per iteration;
- * CG runs in FP64 in transition coordinates (U projected on the conduction
- * orbitals, Z = Phi_c X), the applies in the context precision.  Synchronous.
- * U, Z: device [nrhs][nocc][npw][2] FP64, not aliased; tol: residual 2-norm per
- * system (transition coordinates); resid host [nrhs] (may be NULL); n_iter:
- * iterations; n_exact: iterations that applied the full operator (may be NULL).
+ * inexact Krylov scheme of Sec. 3.3: each CG system applies the full operator
+ * (as wtd_apply_full) until its residual norm falls below lambda_thr and drops
+ * K2d from then on (lambda_thr = 0: never).  The nrhs right-hand sides are
+ * independent CG systems solved side by side; per iteration the systems still
+ * on the full operator form one block apply and those past their switch
+ * another.  CG runs in FP64 in transition coordinates (U projected on the
+ * conduction orbitals, Z = Phi_c X), the applies in the context precision.
+ * Synchronous.  U, Z: device [nrhs][nocc][npw][2] FP64, not aliased; tol:
+ * residual 2-norm per system (transition coordinates); resid host [nrhs] (may
+ * be NULL); n_iter: iterations of the slowest system; n_exact: iterations in
+ * which some system applied the full operator, i.e. the largest count of
+ * full-operator iterations of one system (may be NULL).
  * Returns WTD_NOT_CONVERGED (a warning, outputs valid) after max_iter.
  * Errors: WTD_ERR_ARG, WTD_ERR_SHAPE (nrhs outside [1, max_nb]),
  * WTD_ERR_NONFINITE (CG breakdown: the operator is not positive definite).    */
@@ -206,6 +209,26 @@ wtd_status wtd_profile_read(wtd_ctx *ctx, int32_t n, double *ms, int64_t *calls,
 
 /* Device bytes held by the context (orbital fields, tables and workspace).      */
 wtd_status wtd_workspace_bytes(const wtd_ctx *ctx, size_t *bytes);
+
+/* Process-wide cap on the device memory one context may hold (its workspace,
+ * tables and the buffers a first backward call or Davidson adds): a context
+ * created afterwards whose allocations would pass `bytes` fails with
+ * WTD_ERR_OOM before allocating past it, and so does a later call that would
+ * grow it past the cap.  0 (the default) removes the cap.  Contexts that
+ * already exist keep their memory.  Thread-safe.                                 */
+wtd_status wtd_set_workspace_limit(size_t bytes);
+
+/* Optional input/output checks of one context.  WTD_CHECK_FINITE: every
+ * apply (wtd_apply_liouville, wtd_apply_full, wtd_apply_transition,
+ * wtd_apply_liouville_bwd) and wtd_set_occ scan their device inputs, and the
+ * applies their outputs, for NaN and infinity and return WTD_ERR_NONFINITE
+ * naming the array.  The scans synchronise with the context stream, so a
+ * context with checks on cannot be captured in a HIP graph.  flags = 0 turns
+ * them off (the default).  wtd_create always checks the system arrays
+ * (eps_occ, eps_cond, c_occ, c_cond, fxc) and returns WTD_ERR_NONFINITE.
+ * Errors: WTD_ERR_ARG (null context, unknown flag).                              */
+enum { WTD_CHECK_FINITE = 1 };
+wtd_status wtd_set_checks(wtd_ctx *ctx, uint32_t flags);
 
 const char *wtd_last_error(void);
 

@@ -11,6 +11,7 @@
 //   7. r_bv = sphere coefficients of R_bv   (plane + stick pass, unpacking)
 //   8. Q = Phi_c^T r ; T = (eps_c - eps_v) S + Q ; la = Phi_c T
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -85,6 +86,9 @@ struct wtd_ctx {
   // are kept from one apply to the next until the orbitals change.
   bool tau_cache = false;
   bool tau_valid = false;
+  // layout the kept pair potentials were written in (4-pair interleaved or
+  // [pair][N_r]); a later apply that reads the other layout forms them again
+  bool tau_il = false;
   void* wst = nullptr;       // [max packs][n0][nw] complex
   void* dst = nullptr;       // [pair chunk][n0][nd] complex
   void* ag = nullptr;        // [max_nb][nocc][2 npw]
@@ -115,6 +119,8 @@ struct wtd_ctx {
   int* pidx = nullptr;       // [nocc][nocc]
   // Row-blocked exchange (large Nocc): the pair triangle is split into blocks of
   // row_block occupied rows; tau then holds the pairs of one block pair only.
+  uint32_t checks = 0;       // WTD_CHECK_* flags of wtd_set_checks
+  unsigned* flag = nullptr;  // device word of the non-finite check
   int row_block = 0;         // 0: all pairs at once
   struct BlockPair {
     int A0, nA, B0, nB, diag;
@@ -131,8 +137,16 @@ namespace {
 // groups over which the orbital loop of the trial transform is split
 constexpr int kDrhoGroups = 8;
 
+// device memory one context may hold (wtd_set_workspace_limit; 0: no cap)
+std::atomic<size_t> g_workspace_limit{0};
+
 void* dalloc(wtd_ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  const size_t cap = g_workspace_limit.load();
+  if (cap != 0 && c->total_bytes + bytes > cap)
+    throw StatusError{WTD_ERR_OOM, "context workspace would exceed the limit of " +
+                                       std::to_string(cap) + " bytes (" +
+                                       std::to_string(c->total_bytes + bytes) + " needed so far)"};
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
@@ -161,6 +175,24 @@ void h2d(wtd_ctx* c, void* dst, const void* src, size_t bytes) {
 template <typename T>
 void upload(wtd_ctx* c, void* dst, const std::vector<T>& h) {
   h2d(c, dst, h.data(), h.size() * sizeof(T));
+}
+
+// Synchronous scan of a device array for NaN / infinity: WTD_ERR_NONFINITE names it.
+template <typename T>
+void require_finite(wtd_ctx* c, const T* x, int64_t n, const char* what) {
+  WTD_HIP(hipMemsetAsync(c->flag, 0, sizeof(unsigned), c->stream));
+  launch_flag_nonfinite<T>(x, n, c->flag, c->stream);
+  unsigned h = 0;
+  WTD_HIP(hipMemcpyAsync(&h, c->flag, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  WTD_HIP(hipStreamSynchronize(c->stream));
+  WTD_REQUIRE(h == 0, WTD_ERR_NONFINITE, std::string("non-finite values in ") + what);
+}
+
+void require_finite_any(wtd_ctx* c, const void* x, int64_t n, const char* what) {
+  if (c->prec == WTD_FP64)
+    require_finite<double>(c, (const double*)x, n, what);
+  else
+    require_finite<float>(c, (const float*)x, n, what);
 }
 
 // ---------------------------------------------------------------- profiling
@@ -389,6 +421,16 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   const int64_t nr = c->g.nr;
   const size_t K = 2 * (size_t)npw;
   hipStream_t s = c->stream;
+
+  // every system array must be finite
+  c->flag = (unsigned*)dalloc(c, sizeof(unsigned));
+  for (int v = 0; v < nocc; ++v)
+    WTD_REQUIRE(std::isfinite(sys->eps_occ[v]), WTD_ERR_NONFINITE, "non-finite eps_occ");
+  for (int ci = 0; ci < nc; ++ci)
+    WTD_REQUIRE(std::isfinite(sys->eps_cond[ci]), WTD_ERR_NONFINITE, "non-finite eps_cond");
+  require_finite<double>(c, sys->c_occ, (int64_t)nocc * K, "c_occ");
+  require_finite<double>(c, sys->c_cond, (int64_t)nc * K, "c_cond");
+  if (sys->fxc) require_finite<double>(c, sys->fxc, nr, "fxc");
 
   // orbitals in the working precision; weighted conduction copy for <phi_c|.>
   c->c_occ = dalloc(c, (size_t)nocc * K * sizeof(T));
@@ -667,7 +709,7 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   // of kTauIl pairs when the round-robin contraction reads them (a chunk starts
   // on a whole group, so its groups start at field 2 p0 in either layout)
   const bool il = contract_rr_applies<T>(g, nb, nocc);
-  if (k1d && !c->row_block && !(c->tau_cache && c->tau_valid)) {
+  if (k1d && !c->row_block && !(c->tau_cache && c->tau_valid && c->tau_il == il)) {
     WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
                 WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
     for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
@@ -683,6 +725,7 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
                                   (T*)c->tau + (int64_t)2 * p0 * g.nr, s, il);
     }
     c->tau_valid = c->tau_cache;
+    c->tau_il = il;
   }
   // 6. R
   prof_next(c, 6);
@@ -691,7 +734,7 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
     launch_zero<T>((T*)c->R, (int64_t)nb * nocc * g.nr, s);
   } else if (!launch_contract_mfma<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau,
                                (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)ck,
-                               (T)c->alpha, k1e, k1d, (T*)c->R, s))
+                               (T)c->alpha, k1e, k1d, (T*)c->R, s, il))
     launch_contract<T>(g, nb, nocc, (const T*)c->phi, (const T*)c->at, (const T*)c->tau, c->pidx,
                        (const T*)c->vh, (const T*)c->drho, (const T*)c->fxc, (T)ck,
                        (T)c->alpha, k1e, k1d, (T*)c->R, s);
@@ -911,7 +954,7 @@ void bwd_impl(wtd_ctx* c, int nb, const T* a, const T* g, T* g_a, T* g_occ) {
     }
     if (!launch_contract_mfma<T>(G, 1, nocc, (const T*)c->phi, (const T*)c->phi,
                                  (const T*)c->tau, nullptr, nullptr, (const T*)c->fxc, (T)0,
-                                 (T)c->alpha, false, true, (T*)c->gamma, s))
+                                 (T)c->alpha, false, true, (T*)c->gamma, s, false))
       launch_contract<T>(G, 1, nocc, (const T*)c->phi, (const T*)c->phi, (const T*)c->tau,
                          c->pidx, nullptr, nullptr, (const T*)c->fxc, (T)0, (T)c->alpha, false,
                          true, (T*)c->gamma, s);
@@ -1235,8 +1278,8 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
 
 // ---------------------------------------------------------------- Z-vector CG (FP64)
 // CG on the full operator in transition coordinates, nrhs systems side by side
-// sharing one apply per iteration; K2d is dropped from the first iteration at
-// which every unconverged residual norm is below lambda_thr (inexact Krylov).
+// with their applies batched; each system drops K2d from its first iteration
+// whose residual norm is below lambda_thr (inexact Krylov, Sec. 3.3).
 wtd_status zvector_impl(wtd_ctx* c, int nrhs, const double* U, double tol, int max_iter,
                         double lambda_thr, double* Z, double* resid, int32_t* n_iter,
                         int32_t* n_exact) {
@@ -1287,17 +1330,45 @@ wtd_status zvector_impl(wtd_ctx* c, int nrhs, const double* U, double tol, int m
     }
     return any;
   };
-  bool use_exact = true;
+  // Each system switches to the operator without K2d on its own, at its first
+  // iteration whose residual norm is below lambda_thr; per iteration the
+  // systems still on the exact operator and those past their switch are
+  // applied as two blocks (gathered into staging rows when not contiguous),
+  // and converged systems get a zero product (their step is zero).
+  std::vector<char> exact(nrhs, 1);
+  double* ps = w.alloc((size_t)nrhs * n);
+  double* aps = w.alloc((size_t)nrhs * n);
+  auto apply_set = [&](const std::vector<int>& set, uint32_t mask) {
+    if (set.empty()) return;
+    const int m = (int)set.size();
+    bool contiguous = true;
+    for (int j = 1; j < m; ++j) contiguous = contiguous && set[j] == set[0] + j;
+    if (contiguous) {
+      apply_transition_any(c, m, p + (int64_t)set[0] * n, ap + (int64_t)set[0] * n, mask);
+      return;
+    }
+    for (int j = 0; j < m; ++j)
+      WTD_HIP(hipMemcpyAsync(ps + (int64_t)j * n, p + (int64_t)set[j] * n, n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    apply_transition_any(c, m, ps, aps, mask);
+    for (int j = 0; j < m; ++j)
+      WTD_HIP(hipMemcpyAsync(ap + (int64_t)set[j] * n, aps + (int64_t)j * n, n * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+  };
   int it = 0, nex = 0;
   while (update_active() && it < max_iter) {
-    if (use_exact && lambda_thr > 0.0) {
-      bool below = true;
-      for (int k = 0; k < nrhs; ++k)
-        if (active[k] && !(std::sqrt(rr[k]) < lambda_thr)) below = false;
-      if (below) use_exact = false;
+    std::vector<int> on_exact, on_approx;
+    for (int k = 0; k < nrhs; ++k) {
+      if (!active[k]) {
+        launch_zero<double>(ap + (int64_t)k * n, n, s);
+        continue;
+      }
+      if (exact[k] && lambda_thr > 0.0 && std::sqrt(rr[k]) < lambda_thr) exact[k] = 0;
+      (exact[k] ? on_exact : on_approx).push_back(k);
     }
-    apply_transition_any(c, nrhs, p, ap, use_exact ? c->mask : (c->mask & ~WTD_TERM_K2D));
-    nex += use_exact ? 1 : 0;
+    apply_set(on_exact, c->mask);
+    apply_set(on_approx, c->mask & ~WTD_TERM_K2D);
+    nex += on_exact.empty() ? 0 : 1;
     launch_col_dots(p, ap, nrhs, n, dots, s);
     WTD_HIP(hipMemcpyAsync(pap.data(), dots, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     WTD_HIP(hipStreamSynchronize(s));
@@ -1420,6 +1491,8 @@ wtd_status wtd_destroy(wtd_ctx* ctx) {
 wtd_status wtd_set_occ(wtd_ctx* ctx, const double* c_occ) {
   return guarded([&]() -> wtd_status {
     WTD_REQUIRE(ctx && c_occ, WTD_ERR_ARG, "null argument");
+    if (ctx->checks & WTD_CHECK_FINITE)
+      require_finite<double>(ctx, c_occ, (int64_t)ctx->nocc * 2 * ctx->npw, "c_occ");
     ctx->tau_valid = false;
     if (ctx->prec == WTD_FP64)
       transform_occ<double>(ctx, c_occ);
@@ -1459,10 +1532,14 @@ wtd_status wtd_apply_liouville(wtd_ctx* ctx, int32_t nb, const void* a, void* la
     WTD_REQUIRE(ctx && a && la, WTD_ERR_ARG, "null argument");
     WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
     WTD_REQUIRE(a != la, WTD_ERR_ARG, "a and la must not alias");
+    const int64_t len = (int64_t)nb * ctx->nocc * 2 * ctx->npw;
+    const bool chk = ctx->checks & WTD_CHECK_FINITE;
+    if (chk) require_finite_any(ctx, a, len, "the trial block a");
     if (ctx->prec == WTD_FP64)
       apply_impl<double>(ctx, nb, (const double*)a, (double*)la, tda_mask(ctx));
     else
       apply_impl<float>(ctx, nb, (const float*)a, (float*)la, tda_mask(ctx));
+    if (chk) require_finite_any(ctx, la, len, "the result la");
     return WTD_OK;
   });
 }
@@ -1472,10 +1549,14 @@ wtd_status wtd_apply_full(wtd_ctx* ctx, int32_t nb, const void* a, void* la) {
     WTD_REQUIRE(ctx && a && la, WTD_ERR_ARG, "null argument");
     WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
     WTD_REQUIRE(a != la, WTD_ERR_ARG, "a and la must not alias");
+    const int64_t len = (int64_t)nb * ctx->nocc * 2 * ctx->npw;
+    const bool chk = ctx->checks & WTD_CHECK_FINITE;
+    if (chk) require_finite_any(ctx, a, len, "the trial block a");
     if (ctx->prec == WTD_FP64)
       apply_impl<double>(ctx, nb, (const double*)a, (double*)la, ctx->mask);
     else
       apply_impl<float>(ctx, nb, (const float*)a, (float*)la, ctx->mask);
+    if (chk) require_finite_any(ctx, la, len, "the result la");
     return WTD_OK;
   });
 }
@@ -1498,7 +1579,11 @@ wtd_status wtd_apply_transition(wtd_ctx* ctx, int32_t nb, const double* X, doubl
     WTD_REQUIRE(ctx && X && T, WTD_ERR_ARG, "null argument");
     WTD_REQUIRE(nb >= 1 && nb <= ctx->max_nb, WTD_ERR_SHAPE, "nb out of range [1, max_nb]");
     WTD_REQUIRE((const void*)X != (void*)T, WTD_ERR_ARG, "X and T must not alias");
+    const int64_t len = (int64_t)nb * ctx->nocc * ctx->nc;
+    const bool chk = ctx->checks & WTD_CHECK_FINITE;
+    if (chk) require_finite<double>(ctx, X, len, "the transition block X");
     apply_transition_any(ctx, nb, X, T, tda_mask(ctx));
+    if (chk) require_finite<double>(ctx, T, len, "the result T");
     return WTD_OK;
   });
 }
@@ -1511,6 +1596,11 @@ wtd_status wtd_apply_liouville_bwd(wtd_ctx* ctx, int32_t nb, const void* a, cons
     WTD_REQUIRE(nb <= 16, WTD_ERR_SHAPE, "the backward apply takes at most 16 trials per call");
     WTD_REQUIRE(g_a != a && g_a != g_la && g_occ != a && g_occ != g_la, WTD_ERR_ARG,
                 "outputs must not alias the inputs");
+    if (ctx->checks & WTD_CHECK_FINITE) {
+      const int64_t len = (int64_t)nb * ctx->nocc * 2 * ctx->npw;
+      require_finite_any(ctx, a, len, "the trial block a");
+      require_finite_any(ctx, g_la, len, "the cotangent g_la");
+    }
     if (ctx->prec == WTD_FP64)
       bwd_impl<double>(ctx, nb, (const double*)a, (const double*)g_la, (double*)g_a,
                        (double*)g_occ);
@@ -1556,6 +1646,20 @@ wtd_status wtd_profile_read(wtd_ctx* ctx, int32_t n, double* ms, int64_t* calls,
       P.calls[i] = 0;
     }
     if (count) *count = Profiler::kStages;
+    return WTD_OK;
+  });
+}
+
+wtd_status wtd_set_workspace_limit(size_t bytes) {
+  g_workspace_limit.store(bytes);
+  return WTD_OK;
+}
+
+wtd_status wtd_set_checks(wtd_ctx* ctx, uint32_t flags) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx, WTD_ERR_ARG, "null context");
+    WTD_REQUIRE((flags & ~(uint32_t)WTD_CHECK_FINITE) == 0, WTD_ERR_ARG, "unknown check flag");
+    ctx->checks = flags;
     return WTD_OK;
   });
 }

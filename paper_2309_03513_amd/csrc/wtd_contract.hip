@@ -594,11 +594,11 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
 
   // response-term inputs of this thread's output elements, loaded during the
   // last rounds: phi[16 K + v_loc][r], v_H[b][r], drho[b][r], f_xc[r]
-  float ph[8][C::PER];
+  float ph[8][C::PER] = {};
   float vhb = 0.f, drb = 0.f, fx = 0.f;
   auto load_response = [&]() {
-    if (k1e) {
-      const int b = b0 + (g_ld & 15);
+    const int b = b0 + (g_ld & 15);
+    if (k1e && b < nb) {
 #pragma unroll
       for (int K = 0; K < 8; ++K)
 #pragma unroll
@@ -635,7 +635,10 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
 #pragma unroll
         for (int it = 0; it < C::PER; ++it) {
           const int c = g_ld + it * (C::THREADS / C::TP);
-          ta[K][it] = at[((int64_t)(b0 + (c & 15)) * nocc + K * 16 + (c >> 4)) * nr + rp];
+          // trials past nb (a ragged last trial tile) enter as zeros
+          ta[K][it] = (b0 + (c & 15) < nb)
+                          ? at[((int64_t)(b0 + (c & 15)) * nocc + K * 16 + (c >> 4)) * nr + rp]
+                          : 0.f;
         }
       __syncthreads();  // s_rowb
 #pragma unroll
@@ -713,7 +716,7 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
       const int v = K * 16 + (c >> 4), b = b0 + (c & 15);
       float val = -alpha * s_t[K * C::NE + C::at(c, p_ld)];
       if (k1e) val += ck * ph[K][it] * vb_resp;
-      R[((int64_t)b * nocc + v) * nr + rp] = val;
+      if (b < nb) R[((int64_t)b * nocc + v) * nr + rp] = val;
     }
 }
 
@@ -885,21 +888,23 @@ __global__ void k_response_rows(int nb, int nocc, int64_t nr, const T* __restric
 
 template <typename T>
 bool contract_rr_applies(const Geometry& g, int nb, int nocc) {
-  return sizeof(T) == 4 && nocc == 128 && nb % 16 == 0 && g.nr % RRTile::TP == 0;
+  // any trial count: a ragged last tile of trials is zero-padded in the kernel,
+  // so the pair-potential layout of a context does not depend on nb
+  return sizeof(T) == 4 && nocc == 128 && nb >= 1 && g.nr % RRTile::TP == 0;
 }
 
 template <typename T>
 bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
                           const T* tau, const T* vh, const T* drho, const T* fxc, T ck, T alpha,
-                          bool k1e, bool k1d, T* R, hipStream_t s) {
+                          bool k1e, bool k1d, T* R, hipStream_t s, bool tau_il) {
   const int nt = (nocc + 15) / 16;
   if (nt > 8) return false;
   if constexpr (sizeof(T) == 4) {
-    if (contract_rr_applies<T>(g, nb, nocc)) {
+    if (tau_il && contract_rr_applies<T>(g, nb, nocc)) {
       const int64_t nt64 = g.nr / RRTile::TP;
       WTD_REQUIRE(nt64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
       const int ntile = (int)nt64;
-      dim3 grid(8 * ((ntile + 7) / 8), nb / 16);
+      dim3 grid(8 * ((ntile + 7) / 8), (nb + 15) / 16);
       hipLaunchKernelGGL(k_contract_rr, grid, dim3(RRTile::THREADS), 0, s, nb, nocc, g.nr, ntile,
                          (const float*)phi, (const float*)at, (const float*)tau, (const float*)vh,
                          (const float*)drho, (const float*)fxc, (float)ck, (float)alpha, (int)k1e,
@@ -947,11 +952,11 @@ template bool contract_rr_applies<float>(const Geometry&, int, int);
 template bool contract_rr_applies<double>(const Geometry&, int, int);
 template bool launch_contract_mfma<float>(const Geometry&, int, int, const float*, const float*,
                                           const float*, const float*, const float*, const float*,
-                                          float, float, bool, bool, float*, hipStream_t);
+                                          float, float, bool, bool, float*, hipStream_t, bool);
 template bool launch_contract_mfma<double>(const Geometry&, int, int, const double*,
                                            const double*, const double*, const double*,
                                            const double*, const double*, double, double, bool,
-                                           bool, double*, hipStream_t);
+                                           bool, double*, hipStream_t, bool);
 
 }  // namespace wtd
 

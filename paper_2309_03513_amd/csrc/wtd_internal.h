@@ -108,14 +108,15 @@ void launch_contract(const Geometry& g, int nb, int nocc, const T* phi, const T*
                      const T* fxc, T ck, T alpha, bool k1e, bool k1d, T* R, hipStream_t s);
 
 // MFMA contraction for Nocc <= 128 (wtd_contract.hip); returns false if not applicable.
-// tau is [pair][N_r] (pairs v <= v' row-major), or, when contract_rr_applies(),
-// the same pairs in the kTauIl-interleaved layout.
+// tau is [pair][N_r] (pairs v <= v' row-major), or, when tau_il is set and
+// contract_rr_applies() (FP32, Nocc = 128, any nb), the same pairs in the
+// kTauIl-interleaved layout read by the round-robin kernel.
 template <typename T>
 bool contract_rr_applies(const Geometry& g, int nb, int nocc);
 template <typename T>
 bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, const T* at,
                           const T* tau, const T* vh, const T* drho, const T* fxc, T ck, T alpha,
-                          bool k1e, bool k1d, T* R, hipStream_t s);
+                          bool k1e, bool k1d, T* R, hipStream_t s, bool tau_il);
 
 // Block form of the exchange contraction for large Nocc (wtd_contract.hip):
 // R = c_K phi (v_H + f_xc drho) first, then per row block pair (A, B)
@@ -173,6 +174,9 @@ template <typename Tin, typename Tout>
 void launch_convert(const Tin* in, Tout* out, int64_t n, hipStream_t s);
 template <typename T>
 void launch_zero(T* p, int64_t n, hipStream_t s);
+// *flag |= 1 if x[0..n) holds a NaN or an infinity
+template <typename T>
+void launch_flag_nonfinite(const T* x, int64_t n, unsigned* flag, hipStream_t s);
 void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_float,
                            const double* X, const double* eps_occ, const double* eps_cond,
                            bool with_d, double* T, hipStream_t s);

@@ -1213,6 +1213,29 @@ void launch_zero(T* p, int64_t n, hipStream_t s) {
 template void launch_zero<float>(float*, int64_t, hipStream_t);
 template void launch_zero<double>(double*, int64_t, hipStream_t);
 
+namespace {
+// flag = 1 if any of x[0..n) is a NaN or an infinity (flag zeroed beforehand)
+template <typename T>
+__global__ void k_flag_nonfinite(const T* __restrict__ x, int64_t n, unsigned* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad = bad || !isfinite(x[i]);
+  if (bad) atomicOr(flag, 1u);
+}
+}  // namespace
+
+template <typename T>
+void launch_flag_nonfinite(const T* x, int64_t n, unsigned* flag, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_flag_nonfinite<T>), dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+  WTD_HIP(hipGetLastError());
+}
+
+template void launch_flag_nonfinite<float>(const float*, int64_t, unsigned*, hipStream_t);
+template void launch_flag_nonfinite<double>(const double*, int64_t, unsigned*, hipStream_t);
+
 void launch_transition_out(int nb, int nocc, int nc, const void* Q, bool q_is_float,
                            const double* X, const double* eo, const double* ec, bool with_d,
                            double* T, hipStream_t s) {

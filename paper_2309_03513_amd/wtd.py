@@ -27,7 +27,9 @@ TERM_K2E, TERM_K2D, TERM_FULL = 8, 16, 31
 
 EXPORTS = ["wtd_debug_gemm", "wtd_create", "wtd_destroy", "wtd_set_occ", "wtd_apply_liouville",
            "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson", "wtd_cache_pairs", "wtd_autotune", "wtd_apply_full", "wtd_solve_zvector",
-           "wtd_profile_enable", "wtd_profile_read", "wtd_workspace_bytes", "wtd_last_error"]
+           "wtd_profile_enable", "wtd_profile_read", "wtd_workspace_bytes", "wtd_set_workspace_limit",
+           "wtd_set_checks", "wtd_last_error"]
+CHECK_FINITE = 1
 
 
 class WtdError(RuntimeError):
@@ -83,6 +85,8 @@ def load_library(path: str = LIB_PATH):
     lib.wtd_profile_enable.argtypes = [vp, i32]
     lib.wtd_profile_read.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.wtd_workspace_bytes.argtypes = [vp, vp]
+    lib.wtd_set_workspace_limit.argtypes = [ctypes.c_size_t]
+    lib.wtd_set_checks.argtypes = [vp, ctypes.c_uint32]
     lib.wtd_debug_gemm.argtypes = [ctypes.c_int, i32, i32, i32, vp, i32, vp, i32, i32, vp, i32, vp]
     lib.wtd_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -96,6 +100,11 @@ def _check(status):
     if status < 0:
         raise WtdError(status, load_library().wtd_last_error().decode())
     return status
+
+
+def set_workspace_limit(nbytes):
+    """Cap the device memory of contexts created afterwards (0: no cap)."""
+    _check(load_library().wtd_set_workspace_limit(int(nbytes)))
 
 
 def _torch():
@@ -184,6 +193,10 @@ class Liouville:
             self.close()
         except Exception:
             pass
+
+    def set_checks(self, finite=True):
+        """Scan inputs and outputs of every apply for NaN / infinity (synchronous)."""
+        _check(self._lib.wtd_set_checks(self._handle(), CHECK_FINITE if finite else 0))
 
     def workspace_bytes(self):
         v = ctypes.c_size_t()

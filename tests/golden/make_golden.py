@@ -1,6 +1,6 @@
 """Write oracle eigenvalue references for the seeded systems (calls only oracle/ and gen/).
 
-usage: python tests/golden/make_golden.py c1 [c2 ...]
+usage: python tests/golden/make_golden.py c1 [c2 p5 c3rows ...]
 """
 import json
 import os
@@ -16,11 +16,40 @@ import oracle  # noqa: E402
 from gen import CONFIGS, make_system  # noqa: E402
 
 
+# sampled output rows of the 108^3 / Nocc = 432 system: the exchange and the
+# response term separately, for the seeded two-trial block of gen.trials_random
+C3_ROWS = [0, 215, 431]
+C3_NB = 2
+
+
+def c3_rows():
+    import oracle.planewave as pw
+    pw._WORKERS = len(os.sched_getaffinity(0))
+    from gen import trials_random
+    s = make_system(CONFIGS["c3"])
+    a = trials_random(s, C3_NB)
+    t0 = time.time()
+
+    def say(msg):
+        print(f"[c3rows] {msg} t={time.time() - t0:.0f}s", flush=True)
+
+    k1d = oracle.apply_liouville(s, a, terms=oracle.TERM_K1D, rows=C3_ROWS, progress=say)
+    k1e = oracle.apply_liouville(s, a, terms=oracle.TERM_K1E, rows=C3_ROWS, progress=say)
+    path = os.path.join(HERE, "rows_c3.npz")
+    np.savez(path, rows=np.asarray(C3_ROWS), nb=C3_NB, k1d=k1d, k1e=k1e,
+             source=np.asarray("oracle.apply_liouville(terms=K1D | K1E, rows) on "
+                               "gen.trials_random(gen.make_system(CONFIGS['c3']), 2)"))
+    say(f"wrote {path}")
+
+
 def main(names):
     for name in names:
+        if name == "c3rows":
+            c3_rows()
+            continue
         cfg = CONFIGS[name]
         s = make_system(cfg)
-        tol = 1e-8 if name == "c1" else 1e-7
+        tol = 1e-8 if name in ("c1", "p5") else 1e-7
         t0 = time.time()
         calls = [0]
 

@@ -91,3 +91,55 @@ def test_row_blocked_refuses_pair_cache(systems, monkeypatch):
         L.cache_pairs(True)
     L.cache_pairs(False)
     L.close()
+
+
+def test_cached_pairs_across_block_sizes_nocc128(systems):
+    """Nocc = 128 in FP32 keeps its pair potentials in the layout the
+    round-robin contraction reads; applies with block sizes that are not whole
+    16-trial tiles (8, 15, 1) reuse them and must equal uncached applies."""
+    s = systems("p5")
+    a16 = trials_random(s, 16)
+    say("pair cache p5 fp32: nb 16 -> 8 -> 15 -> 1 -> 16")
+    L = _ctx(s, 16, "fp32")
+    ref = {nb: L.apply(a16[:nb]).clone() for nb in (16, 8, 15, 1)}
+    L.cache_pairs(True)
+    for nb in (16, 8, 15, 1, 16, 8):
+        got = L.apply(a16[:nb]).clone()
+        torch.cuda.synchronize()
+        assert _same(got, ref[nb]), nb
+    L.close()
+    for nb in (8, 15):
+        err = rel_err(to_complex(ref[nb]), oracle.apply_liouville(s, a16[:nb]))
+        say(f"  nb={nb} rel err vs oracle {err:.3e}")
+        assert err <= 2e-5
+
+
+def test_davidson_nocc128_fp32_shrinking_block(systems):
+    """A Nocc = 128 FP32 Davidson run keeps its pair potentials and replays its
+    applies from graphs while the active block shrinks below 16 (the lowest
+    Ritz vectors converge first): its roots must match the oracle's FP64
+    Davidson roots stored in tests/golden/roots_p5.json within 1 meV, and the
+    same run without graphs must give the same roots bit for bit."""
+    import json
+    import os
+    from paper_2309_03513_amd import Liouville
+    s = systems("p5")
+    path = os.path.join(os.path.dirname(__file__), "golden", "roots_p5.json")
+    ref = np.asarray(json.load(open(path))["roots_hartree"])
+    nroots = len(ref)
+    say(f"davidson p5 fp32 nroots={nroots} nb=16 (graphs on, then off)")
+    out = []
+    for graphs in ("1", "0"):
+        os.environ["WTD_DAVIDSON_GRAPHS"] = graphs
+        try:
+            L = Liouville(s, max_nb=16, precision="fp32")
+            om, _, res, nit, st = L.davidson(nroots, 16, tol=1e-5, max_iter=80, want_x=False)
+            L.close()
+        finally:
+            os.environ.pop("WTD_DAVIDSON_GRAPHS", None)
+        d = np.abs(om - ref)
+        say(f"  graphs={graphs}: iterations {nit}, status {st}, max |d omega| {d.max():.3e} Ha")
+        assert st == 0
+        assert d.max() <= 3.674932e-5
+        out.append(om)
+    assert np.array_equal(out[0], out[1])

@@ -90,13 +90,18 @@ def test_full_operator_row_blocked(systems, monkeypatch, cfg, rb, rows):
 
 
 def _rhs(s, nrhs, seed):
+    # right-hand sides of different sizes, so that with lambda_thr > 0 the
+    # systems cross the threshold at different iterations
     nocc, nc = s.c_occ.shape[0], s.c_cond.shape[0]
     X = np.random.default_rng(seed).standard_normal((nrhs, nocc, nc))
+    X *= (0.3 ** np.arange(nrhs))[:, None, None]
     return X, np.einsum("bvc,cm->bvm", X, s.c_cond)
 
 
 @pytest.mark.parametrize("cfg,prec,nrhs,lam,tol", [("c1", "fp64", 2, 0.0, 1e-9),
                                                    ("c1", "fp64", 1, 1e-3, 1e-9),
+                                                   ("c1", "fp64", 3, 1e-3, 1e-9),
+                                                   ("p2", "fp64", 2, 3e-3, 1e-9),
                                                    ("p2", "fp64", 3, 0.0, 1e-9),
                                                    ("c1", "fp32", 2, 0.0, 1e-4)])
 def test_zvector_cg_matches_oracle(systems, cfg, prec, nrhs, lam, tol):

@@ -231,3 +231,48 @@ def test_error_codes(systems):
     om, x, r, nit, st = L.davidson(2, 2, tol=1e-14, max_iter=1)
     assert st == 1                      # WTD_NOT_CONVERGED is a warning
     L.close()
+
+
+@pytest.mark.parametrize("cfg,prec,tol", [("c1", "fp64", 1e-10), ("p1", "fp64", 1e-10),
+                                          ("p5", "fp64", 1e-10), ("c1", "fp32", 2e-5),
+                                          ("p5", "fp32", 2e-5)])
+def test_apply_stress_per_term(systems, cfg, prec, tol):
+    """alpha = 25, c_K = 200: the response and exchange terms outweigh D, so a
+    mistake in either shows at the whole-operator scale too.  Per term and
+    whole, element by element (the bound covers max |got - ref| / max |ref| as
+    well as the relative Frobenius norm of each trial)."""
+    s = systems(cfg, alpha=25.0, c_k=200.0)
+    nb = s.cfg.nb
+    a = trials_random(s, nb)
+    for term in ("K1E", "K1D", "ALL"):
+        L = _ctx(s, nb, prec, TERMS[term])
+        got = to_complex(L.apply(a))
+        L.close()
+        ref = oracle.apply_liouville(s, a, terms=TERMS[term])
+        err = rel_err(got, ref)
+        say(f"stress alpha=25 c_K=200 cfg={cfg} {prec} term={term}: err {err:.3e}")
+        assert err <= tol
+
+
+def test_apply_fp32_with_g0_kernel(systems):
+    """A Coulomb kernel value at G = 0 in the FP32 path: the apply matches the
+    oracle and the lowest roots move by -alpha v_g0 / Omega (the closed form of
+    the G = 0 term for in-span trials)."""
+    s = systems("c1", v_g0=0.9)
+    s0 = systems("c1")
+    nb = s.cfg.nb
+    a, _ = trials_in_span(s, nb)
+    say("apply fp32 c1 v_g0 = 0.9")
+    L = _ctx(s, nb, "fp32")
+    got = to_complex(L.apply(a))
+    err = rel_err(got, oracle.apply_liouville(s, a))
+    om, _, _, _, st = L.davidson(4, 4, tol=1e-5, want_x=False)
+    L.close()
+    L0 = _ctx(s0, nb, "fp32")
+    om0, _, _, _, st0 = L0.davidson(4, 4, tol=1e-5, want_x=False)
+    L0.close()
+    shift = -s.alpha * 0.9 / float(np.prod(s.cell))
+    say(f"  rel err {err:.3e}; root shift {np.max(np.abs(om - om0 - shift)):.3e} off the closed form")
+    assert err <= 2e-5
+    assert st == 0 and st0 == 0
+    assert np.max(np.abs(om - om0 - shift)) <= 3.674932e-5
