@@ -16,8 +16,8 @@ import oracle  # noqa: E402
 from gen import CONFIGS, make_system  # noqa: E402
 
 
-# sampled output rows of the 108^3 / Nocc = 432 system: the exchange and the
-# response term separately, for the seeded two-trial block of gen.trials_random
+# sampled output rows of the 108^3 / Nocc = 432 system: the D, exchange and
+# response terms separately, for the seeded two-trial block of gen.trials_random
 C3_ROWS = [0, 215, 431]
 C3_NB = 2
 
@@ -33,11 +33,12 @@ def c3_rows():
     def say(msg):
         print(f"[c3rows] {msg} t={time.time() - t0:.0f}s", flush=True)
 
+    d = oracle.apply_liouville(s, a, terms=oracle.TERM_D, rows=C3_ROWS, progress=say)
     k1d = oracle.apply_liouville(s, a, terms=oracle.TERM_K1D, rows=C3_ROWS, progress=say)
     k1e = oracle.apply_liouville(s, a, terms=oracle.TERM_K1E, rows=C3_ROWS, progress=say)
     path = os.path.join(HERE, "rows_c3.npz")
-    np.savez(path, rows=np.asarray(C3_ROWS), nb=C3_NB, k1d=k1d, k1e=k1e,
-             source=np.asarray("oracle.apply_liouville(terms=K1D | K1E, rows) on "
+    np.savez(path, rows=np.asarray(C3_ROWS), nb=C3_NB, d=d, k1d=k1d, k1e=k1e,
+             source=np.asarray("oracle.apply_liouville(terms=D, K1D, K1E separately, rows) on "
                                "gen.trials_random(gen.make_system(CONFIGS['c3']), 2)"))
     say(f"wrote {path}")
 
