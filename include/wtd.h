@@ -199,6 +199,31 @@ wtd_status wtd_davidson(wtd_ctx *ctx, int32_t nroots, int32_t nb, double tol, in
                         int32_t max_sub, const double *guess, double *omega, double *x,
                         double *resid, int32_t *n_iter);
 
+/* Size of the static device array wtd_davidson_noalloc works in.             */
+#define WTD_DAVIDSON_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* wtd_davidson for callers that cannot allocate device memory (code around
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same block Davidson with the same arguments, outputs, warnings and errors,
+ * but every buffer of the run (basis and its products, subspace matrix and
+ * eigenvectors, Ritz vectors, residuals, corrections, the projected guess and
+ * the FP64 copy of the conduction orbitals an FP32 context needs) is carved
+ * from one static device array of WTD_DAVIDSON_SCRATCH_BYTES that every GPU
+ * the library runs on holds until the process ends.  It calls no hipMalloc,
+ * hipFree or other allocating routine and instantiates no HIP graph (every
+ * apply runs eagerly on the workspace wtd_create allocated).  Nothing in the
+ * array has to start at zero.  Every call on one GPU uses that GPU's single
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (from other threads or on other contexts) race, and the caller must
+ * serialise them.  A run needs about 8 [(2 max_sub + 5 nb) nocc ncond
+ * + 3 max_sub^2 + 2 ncond npw] bytes (36 MB at nocc = ncond = 128, nb = 16,
+ * max_sub = 64, FP32 bulk, no guess).
+ * Errors: as wtd_davidson, plus WTD_ERR_SHAPE naming the bytes needed when the
+ * run does not fit in the array.                                               */
+wtd_status wtd_davidson_noalloc(wtd_ctx *ctx, int32_t nroots, int32_t nb, double tol,
+                                int32_t max_iter, int32_t max_sub, const double *guess,
+                                double *omega, double *x, double *resid, int32_t *n_iter);
+
 /* Per-stage timing with HIP events on the context stream (for profiling).
  * wtd_profile_enable(ctx, 1) starts recording; wtd_profile_read copies the
  * accumulated milliseconds and call counts of up to n stages and their names

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -128,6 +129,8 @@ struct wtd_ctx {
   };
   std::vector<BlockPair> bpairs;
   wtd::Profiler prof;
+  // this device's copy of the static Davidson scratch array (wtd_davidson_noalloc)
+  void* scratch = nullptr;
 };
 
 namespace wtd {
@@ -136,6 +139,32 @@ namespace {
 
 // groups over which the orbital loop of the trial transform is split
 constexpr int kDrhoGroups = 8;
+
+// Device memory of wtd_davidson_noalloc, for callers that cannot allocate: one
+// statically sized array that every GPU the library runs on holds until the
+// process ends.  Its name is only a host-side stand-in; host code passes the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = WTD_DAVIDSON_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of its copy of scratch
+
+// Address of the scratch array on `device`, which must be the current device.
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    throw StatusError{WTD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e)};
+  }
+  g_scratch_ptr.emplace(device, ptr);
+  return ptr;
+}
 
 // device memory one context may hold (wtd_set_workspace_limit; 0: no cap)
 std::atomic<size_t> g_workspace_limit{0};
@@ -1059,13 +1088,29 @@ void autotune_impl(wtd_ctx* c, int nb, int reps, int32_t* chunk_out, int32_t* gr
 }
 
 // ---------------------------------------------------------------- Davidson (FP64)
+// Buffers of one Davidson or CG run: hipMalloc'ed and freed at the end, or (with
+// an arena) carved from the static scratch array in 256-byte aligned pieces.
+constexpr size_t dav_piece(size_t n) { return (std::max<size_t>(n, 2) * sizeof(double) + 255) / 256 * 256; }
+
 struct DavWork {
   wtd_ctx* c;
   std::vector<void*> mem;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   ~DavWork() {
     for (void* p : mem) (void)hipFree(p);
   }
   double* alloc(size_t n) {
+    if (arena) {
+      const size_t b = dav_piece(n);
+      if (used + b > cap)
+        throw StatusError{WTD_ERR_SHAPE, "Davidson scratch exhausted (" +
+                                             std::to_string(used + b) + " of " +
+                                             std::to_string(cap) + " bytes)"};
+      double* p = (double*)(arena + used);
+      used += b;
+      return p;
+    }
     void* p = nullptr;
     if (hipMalloc(&p, std::max<size_t>(n, 2) * sizeof(double)) != hipSuccess) {
       (void)hipGetLastError();
@@ -1076,9 +1121,22 @@ struct DavWork {
   }
 };
 
+// Device bytes of the buffers davidson_impl takes (in the order it takes them);
+// with graph replays it also takes two staging blocks, never in the arena.
+size_t davidson_need(const wtd_ctx* c, int nb, int max_sub, bool guess, bool want_x) {
+  const size_t n = (size_t)c->nocc * c->nc, K = 2 * (size_t)c->npw, ms = max_sub;
+  size_t t = 2 * dav_piece(ms * n) + dav_piece(ms * ms) + dav_piece(ms) + dav_piece(2 * ms * ms) +
+             4 * dav_piece((size_t)nb * n) + dav_piece(nb) + dav_piece(ms) + dav_piece(nb);
+  if (guess) t += dav_piece((size_t)nb * n) + dav_piece((size_t)c->nc * K);
+  if (want_x && c->prec != WTD_FP64) t += dav_piece((size_t)c->nc * K);
+  return t;
+}
+
+// noalloc: every buffer comes from the static scratch array (no hipMalloc,
+// hipFree or graph instantiation); the run is otherwise the same.
 wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_iter, int max_sub,
                          const double* guess, double* omega, double* x, double* resid,
-                         int32_t* n_iter) {
+                         int32_t* n_iter, bool noalloc = false) {
   hipStream_t s = c->stream;
   const int nocc = c->nocc, nc = c->nc, npw = c->npw;
   const int64_t n = (int64_t)nocc * nc;
@@ -1088,6 +1146,18 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
   max_sub = (int)std::min<int64_t>(max_sub, n);
   WTD_REQUIRE(max_sub <= 256, WTD_ERR_SHAPE, "max_sub must not exceed 256");
   DavWork w{c, {}};
+  if (noalloc) {
+    const size_t need = davidson_need(c, nb, max_sub, guess != nullptr, x != nullptr);
+    WTD_REQUIRE(need <= kScratchBytes, WTD_ERR_SHAPE,
+                "wtd_davidson_noalloc needs " + std::to_string(need) +
+                    " bytes of scratch for this system and block (nocc*ncond = " +
+                    std::to_string(n) + ", nb = " + std::to_string(nb) + ", max_sub = " +
+                    std::to_string(max_sub) + "); the static array holds " +
+                    std::to_string(kScratchBytes));
+    WTD_REQUIRE(c->scratch != nullptr, WTD_ERR_HIP, "scratch array address not set");
+    w.arena = (char*)c->scratch;
+    w.cap = kScratchBytes;
+  }
   // every apply of the run sees the same orbitals: form the pair potentials once
   struct KeepPairs {
     wtd_ctx* c;
@@ -1181,7 +1251,7 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
       for (auto& e : ex) (void)hipGraphExecDestroy(e.second);
     }
   } graphs;
-  bool use_graphs = !c->prof.on && s != nullptr;
+  bool use_graphs = !c->prof.on && s != nullptr && !noalloc;
   if (const char* e = std::getenv("WTD_DAVIDSON_GRAPHS")) use_graphs = use_graphs && std::atoi(e) != 0;
   double* gx = use_graphs ? w.alloc((size_t)nb * n) : nullptr;
   double* gt = use_graphs ? w.alloc((size_t)nb * n) : nullptr;
@@ -1449,6 +1519,7 @@ wtd_status wtd_create(const wtd_system* sys, int32_t max_nb, void* hip_stream, w
     std::unique_ptr<wtd_ctx> c(new wtd_ctx());
     c->stream = (hipStream_t)hip_stream;
     WTD_HIP(hipGetDevice(&c->device));
+    c->scratch = scratch_address(c->device);
     c->prec = sys->prec;
     c->mask = sys->term_mask;
     c->npw = sys->npw;
@@ -1620,6 +1691,19 @@ wtd_status wtd_davidson(wtd_ctx* ctx, int32_t nroots, int32_t nb, double tol, in
     WTD_REQUIRE(max_iter >= 1 && tol > 0.0, WTD_ERR_ARG, "need max_iter >= 1 and tol > 0");
     return davidson_impl(ctx, nroots, nb, tol, max_iter, max_sub, guess, omega, x, resid,
                          n_iter);
+  });
+}
+
+wtd_status wtd_davidson_noalloc(wtd_ctx* ctx, int32_t nroots, int32_t nb, double tol,
+                                int32_t max_iter, int32_t max_sub, const double* guess,
+                                double* omega, double* x, double* resid, int32_t* n_iter) {
+  return guarded([&]() -> wtd_status {
+    WTD_REQUIRE(ctx && omega, WTD_ERR_ARG, "null argument");
+    WTD_REQUIRE(nroots >= 1 && nb >= nroots && nb <= ctx->max_nb, WTD_ERR_SHAPE,
+                "need 1 <= nroots <= nb <= max_nb");
+    WTD_REQUIRE(max_iter >= 1 && tol > 0.0, WTD_ERR_ARG, "need max_iter >= 1 and tol > 0");
+    return davidson_impl(ctx, nroots, nb, tol, max_iter, max_sub, guess, omega, x, resid,
+                         n_iter, true);
   });
 }
 

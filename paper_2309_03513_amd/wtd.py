@@ -26,7 +26,7 @@ TERM_D, TERM_K1E, TERM_K1D, TERM_ALL = 1, 2, 4, 7
 TERM_K2E, TERM_K2D, TERM_FULL = 8, 16, 31
 
 EXPORTS = ["wtd_debug_gemm", "wtd_create", "wtd_destroy", "wtd_set_occ", "wtd_apply_liouville",
-           "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson", "wtd_cache_pairs", "wtd_autotune", "wtd_apply_full", "wtd_solve_zvector",
+           "wtd_apply_transition", "wtd_apply_liouville_bwd", "wtd_davidson", "wtd_davidson_noalloc", "wtd_cache_pairs", "wtd_autotune", "wtd_apply_full", "wtd_solve_zvector",
            "wtd_profile_enable", "wtd_profile_read", "wtd_workspace_bytes", "wtd_set_workspace_limit",
            "wtd_set_checks", "wtd_last_error"]
 CHECK_FINITE = 1
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     lib.wtd_apply_transition.argtypes = [vp, i32, vp, vp]
     lib.wtd_apply_liouville_bwd.argtypes = [vp, i32, vp, vp, vp, vp]
     lib.wtd_davidson.argtypes = [vp, i32, i32, f64, i32, i32, vp, vp, vp, vp, vp]
+    lib.wtd_davidson_noalloc.argtypes = [vp, i32, i32, f64, i32, i32, vp, vp, vp, vp, vp]
     lib.wtd_cache_pairs.argtypes = [vp, i32]
     lib.wtd_apply_full.argtypes = [vp, i32, vp, vp]
     lib.wtd_solve_zvector.argtypes = [vp, i32, vp, f64, i32, f64, vp, vp, vp, vp]
@@ -272,6 +273,17 @@ class Liouville:
     def davidson(self, nroots, nb, tol=1e-8, max_iter=100, max_sub=0, guess=None, want_x=True):
         """Returns (omega[nroots] numpy, x [nroots][nocc][npw][2] float64 tensor or None,
         resid numpy, n_iter, status)."""
+        return self._davidson(self._lib.wtd_davidson, nroots, nb, tol, max_iter, max_sub, guess,
+                              want_x)
+
+    def davidson_noalloc(self, nroots, nb, tol=1e-8, max_iter=100, max_sub=0, guess=None,
+                         want_x=True):
+        """wtd_davidson_noalloc: the same run in the library's static device array
+        (no device allocation by the library; x, if wanted, is allocated here)."""
+        return self._davidson(self._lib.wtd_davidson_noalloc, nroots, nb, tol, max_iter, max_sub,
+                              guess, want_x)
+
+    def _davidson(self, fn, nroots, nb, tol, max_iter, max_sub, guess, want_x):
         torch = _torch()
         omega = np.zeros(nroots)
         resid = np.zeros(nroots)
@@ -279,7 +291,7 @@ class Liouville:
         x = torch.empty((nroots, self.nocc, self.npw, 2), dtype=torch.float64,
                         device=self.device) if want_x else None
         g = as_coeff_tensor(guess, torch.float64, self.device) if guess is not None else None
-        st = _check(self._lib.wtd_davidson(
+        st = _check(fn(
             self._handle(), int(nroots), int(nb), float(tol), int(max_iter), int(max_sub),
             _ptr(g), omega.ctypes.data_as(ctypes.c_void_p), _ptr(x),
             resid.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nit)))
