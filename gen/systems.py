@@ -90,6 +90,10 @@ CONFIGS = {
                  nb=4, nroots=2, seed=16),
     "p7": Config("p7", *_cubic(11.25, 60), ecut_ry=40.0, nocc=34, ncond=10, gap=0.15,
                  nb=3, nroots=2, seed=17),
+    # the batch's smallest grid (48^3 at its spacing and cutoff) with more than
+    # 128 occupied orbitals (row-blocked exchange, ragged last block) and an odd block
+    "p8": Config("p8", *_cubic(9.0, 48), ecut_ry=40.0, nocc=140, ncond=8, gap=0.15,
+                 nb=5, nroots=2, seed=18),
     # more than 128 occupied orbitals (row-blocked exchange: blocks 64, 64, 16)
     "p4": Config("p4", *_cubic(12.0, 36), ecut_ry=20.0, nocc=144, ncond=24, gap=0.15,
                  nb=3, nroots=3, seed=14),

@@ -187,8 +187,11 @@ wtd_status wtd_apply_liouville_bwd(wtd_ctx *ctx, int32_t nb, const void *a, cons
 /* Block Davidson for the nroots lowest eigenpairs of L (Sec. 4; normalisation
  * sum_v <x_v|x_v> = 1 of Eq. ltda).  Synchronous.  Where the exchange is not
  * row-blocked the pair potentials are formed once per call and reused by every
- * apply of the run (as with wtd_cache_pairs).  On a non-null stream the applies
- * after the first are replayed from one HIP graph per block size.
+ * apply of the run (as with wtd_cache_pairs).  Each iteration is one device-side
+ * step (corrections, their orthonormalisation, the block apply, the subspace
+ * matrix and its eigenpairs, Ritz vectors and residuals) followed by one read of
+ * the Ritz values and residual norms; on a non-null stream every step after the
+ * first is replayed from a HIP graph captured once per (basis size, block size).
  * nb: block size (nroots <= nb <= max_nb); tol: residual 2-norm per root;
  * max_sub: basis cap before restart (<= 0: 4*nb); guess: device
  * [nb][nocc][npw][2] FP64 or NULL (lowest unit transitions).
@@ -216,7 +219,7 @@ wtd_status wtd_davidson(wtd_ctx *ctx, int32_t nroots, int32_t nb, double tol, in
  * array, which keeps the last call's contents: calls that overlap on one GPU
  * (from other threads or on other contexts) race, and the caller must
  * serialise them.  A run needs about 8 [(2 max_sub + 5 nb) nocc ncond
- * + 3 max_sub^2 + 2 ncond npw] bytes (36 MB at nocc = ncond = 128, nb = 16,
+ * + 21 max_sub^2 + 2 ncond npw] bytes (37 MB at nocc = ncond = 128, nb = 16,
  * max_sub = 64, FP32 bulk, no guess).
  * Errors: as wtd_davidson, plus WTD_ERR_SHAPE naming the bytes needed when the
  * run does not fit in the array.                                               */

@@ -1121,17 +1121,37 @@ struct DavWork {
   }
 };
 
-// Device bytes of the buffers davidson_impl takes (in the order it takes them);
-// with graph replays it also takes two staging blocks, never in the arena.
+// Device bytes of the buffers davidson_impl takes (dav_piece each).
 size_t davidson_need(const wtd_ctx* c, int nb, int max_sub, bool guess, bool want_x) {
   const size_t n = (size_t)c->nocc * c->nc, K = 2 * (size_t)c->npw, ms = max_sub;
-  size_t t = 2 * dav_piece(ms * n) + dav_piece(ms * ms) + dav_piece(ms) + dav_piece(2 * ms * ms) +
-             4 * dav_piece((size_t)nb * n) + dav_piece(nb) + dav_piece(ms) + dav_piece(nb);
+  size_t t = 2 * dav_piece(ms * n)                 // V, W
+             + dav_piece(ms * ms) + dav_piece(ms)   // H, evals
+             + dav_piece(2 * ms * ms)               // evecs (+ rotation scratch)
+             + dav_piece(ms * ms)                   // evecs transposed
+             + 4 * dav_piece((size_t)nb * n)        // Ritz vectors, products, residuals, GEMM rows
+             + dav_piece(nb)                        // residual norms
+             + dav_piece((size_t)nb * ms)           // projection coefficients of a block
+             + dav_piece(ms)                        // coefficients of one candidate
+             + dav_piece(16 * ms * ms)              // split-K partial products
+             + 2 * dav_piece(ms);                   // active list, slot flags (ints)
   if (guess) t += dav_piece((size_t)nb * n) + dav_piece((size_t)c->nc * K);
   if (want_x && c->prec != WTD_FP64) t += dav_piece((size_t)c->nc * K);
   return t;
 }
 
+// Block Davidson (Sec. 4).  Every iteration is one device-side step with no
+// host synchronisation inside it: corrections of the roots that have not
+// converged (the active list is formed on the device from the residual norms),
+// their orthonormalisation against the basis (block Gram-Schmidt twice, as
+// matrix-core GEMMs) and among themselves, the block apply, the subspace matrix
+// V^T W (GEMM), its eigendecomposition, the Ritz vectors and products (GEMMs)
+// and the residuals.  The host reads the Ritz values, residual norms and the
+// kept/dropped flags of the new corrections once per iteration.  A correction
+// whose norm falls below 1e-10 after orthogonalisation keeps its basis slot as
+// a zero vector whose subspace diagonal is set to 1e30 (it never enters the
+// lowest roots), so every step has a shape the host knows before it runs; on a
+// non-null stream the step of each (basis size, block size) is captured once
+// as a HIP graph and replayed.
 // noalloc: every buffer comes from the static scratch array (no hipMalloc,
 // hipFree or graph instantiation); the run is otherwise the same.
 wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_iter, int max_sub,
@@ -1140,6 +1160,8 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
   hipStream_t s = c->stream;
   const int nocc = c->nocc, nc = c->nc, npw = c->npw;
   const int64_t n = (int64_t)nocc * nc;
+  WTD_REQUIRE(n < (1ll << 31), WTD_ERR_SHAPE, "transition space too large");
+  const int ni = (int)n;
   nb = (int)std::min<int64_t>(nb, n);
   if (max_sub <= 0) max_sub = 4 * nb;
   max_sub = std::max(max_sub, 2 * nb);
@@ -1168,24 +1190,28 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
     }
   } keep{c, c->tau_cache};
   if (!c->row_block || c->bpairs.size() == 1) c->tau_cache = true;
-  double* V = w.alloc((size_t)max_sub * n);
-  double* W = w.alloc((size_t)max_sub * n);
-  double* H = w.alloc((size_t)max_sub * max_sub);
-  double* evals = w.alloc(max_sub);
-  double* evecs = w.alloc(2 * (size_t)max_sub * max_sub);
+  const size_t ms = max_sub;
+  double* V = w.alloc(ms * n);
+  double* W = w.alloc(ms * n);
+  double* H = w.alloc(ms * ms);
+  double* evals = w.alloc(ms);
+  double* evecs = w.alloc(2 * ms * ms);
+  double* evecsT = w.alloc(ms * ms);
   double* Xr = w.alloc((size_t)nb * n);
   double* WY = w.alloc((size_t)nb * n);
   double* Rr = w.alloc((size_t)nb * n);
-  double* Tc = w.alloc((size_t)nb * n);
+  double* tmp = w.alloc((size_t)nb * n);
   double* rn2 = w.alloc(nb);
-  double* coef = w.alloc(max_sub);
-  int* active = (int*)w.alloc(nb);
+  double* coefT = w.alloc((size_t)nb * ms);
+  double* coef = w.alloc(ms);
+  const size_t gscr_elems = 16 * ms * ms;
+  double* gscr = w.alloc(gscr_elems);
+  int* active = (int*)w.alloc(ms);
+  int* ok = (int*)w.alloc(ms);
 
-  // guess
-  int m = 0;
+  // guess block in basis slots 0 .. nb-1
   if (guess) {
     // project the G-space guess onto transition coordinates: X = Phi_c^T g
-    std::vector<double> gx((size_t)nb * n);
     double* Sx = w.alloc((size_t)nb * n);
     double* Cw = w.alloc((size_t)nc * 2 * npw);
     if (c->prec == WTD_FP64) {
@@ -1195,7 +1221,7 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
       launch_convert<float, double>((const float*)c->c_condw, Cw, (int64_t)nc * 2 * npw, s);
       launch_gemm<double, true>(nb * nocc, nc, 2 * npw, guess, 2 * npw, Cw, 2 * npw, Sx, nc, s);
     }
-    WTD_HIP(hipMemcpyAsync(Tc, Sx, (size_t)nb * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    WTD_HIP(hipMemcpyAsync(V, Sx, (size_t)nb * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   } else {
     std::vector<int> idx(n);
     for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
@@ -1209,65 +1235,75 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
     });
     std::vector<double> g((size_t)nb * n, 0.0);
     for (int j = 0; j < nb; ++j) g[(size_t)j * n + idx[j]] = 1.0;
-    h2d(c, Tc, g.data(), g.size() * sizeof(double));
+    h2d(c, V, g.data(), g.size() * sizeof(double));
   }
 
-  std::vector<double> h_norm(nb), h_th(max_sub), h_rn(nb);
-  // orthonormalise a block of k candidate rows (at Tc) against V[0..m) and each other,
-  // appending accepted rows to V; returns the number appended.
-  auto orthonormalise_append = [&](int k) -> int {
-    int added = 0;
-    for (int j = 0; j < k; ++j) {
-      double* t = Tc + (int64_t)j * n;
+  // rows T = V[m .. m + na): orthogonalised against V[0 .. m) twice (GEMMs),
+  // then one by one against the rows before them (twice), then normalised or
+  // dropped
+  auto ortho_block = [&](int m, int na) {
+    double* T = V + (int64_t)m * n;
+    if (m > 0) {
       for (int pass = 0; pass < 2; ++pass) {
-        if (m + added > 0) {
-          launch_gram(V, m + added, t, 1, n, coef, 1, s);
-          launch_axpy_cols(t, V, coef, m + added, 1, n, s);
-        }
+        launch_gemm<double, true>(na, m, ni, T, ni, V, ni, coefT, m, s, gscr, gscr_elems);
+        launch_gemm<double, false>(na, ni, m, coefT, m, V, ni, tmp, ni, s);
+        launch_sub_rows(T, tmp, (int64_t)na * n, s);
       }
-      launch_col_norms(t, 1, n, rn2, s);
-      double nrm2 = 0.0;
-      WTD_HIP(hipMemcpyAsync(&nrm2, rn2, sizeof(double), hipMemcpyDeviceToHost, s));
-      WTD_HIP(hipStreamSynchronize(s));
-      const double nrm = std::sqrt(nrm2);
-      if (!(nrm >= 1e-10)) continue;
-      launch_scale_rows(t, 1.0 / nrm, n, s);
-      WTD_HIP(hipMemcpyAsync(V + (int64_t)(m + added) * n, t, n * sizeof(double),
-                             hipMemcpyDeviceToDevice, s));
-      ++added;
     }
-    return added;
+    for (int j = 0; j < na; ++j) {
+      double* t = T + (int64_t)j * n;
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        launch_gram(T, j, t, 1, n, coef, 1, s);
+        launch_axpy_cols(t, T, coef, j, 1, n, s);
+      }
+      launch_normalise_or_drop(t, n, ok, m + j, s);
+    }
+  };
+  // subspace of the first mt basis rows: H, eigenpairs, Ritz vectors, residuals
+  auto finish = [&](int mt) {
+    launch_gemm<double, true>(mt, mt, ni, V, ni, W, ni, H, max_sub, s, gscr, gscr_elems);
+    launch_fix_dropped(H, max_sub, ok, mt, s);
+    launch_jacobi_eig(H, mt, max_sub, evals, evecs, s);
+    const int k = std::min(nb, mt);
+    launch_transpose(evecs, mt, mt, evecsT, s);
+    launch_gemm<double, false>(k, ni, mt, evecsT, mt, V, ni, Xr, ni, s);
+    launch_gemm<double, false>(k, ni, mt, evecsT, mt, W, ni, WY, ni, s);
+    launch_residual(WY, Xr, evals, k, n, Rr, rn2, s);
+  };
+  // one iteration after the first: corrections of the na active roots into
+  // V[m .. m + na), their orthonormalisation, the apply and the new subspace
+  const double tol2 = tol * tol;
+  auto step = [&](int m, int na, int kprev) {
+    launch_active_list(rn2, kprev, tol2, active, s);
+    launch_precondition(Rr, evals, c->diag, na, n, active, V + (int64_t)m * n, s);
+    ortho_block(m, na);
+    apply_transition_any(c, na, V + (int64_t)m * n, W + (int64_t)m * n, tda_mask(c));
+    finish(m + na);
   };
 
-  // The applies of the run after the first (which forms the pair potentials
-  // when they are kept) are replayed from one HIP graph per block size k,
-  // captured on fixed staging buffers: the k new basis vectors are copied in,
-  // the graph runs the whole apply, the products are copied out
-  // (WTD_DAVIDSON_GRAPHS=0 applies eagerly; so does a run with profiling on or
-  // on the null stream, which cannot be captured).
   struct Graphs {
     std::map<int, hipGraphExec_t> ex;
     ~Graphs() {
       for (auto& e : ex) (void)hipGraphExecDestroy(e.second);
     }
   } graphs;
+  // (WTD_DAVIDSON_GRAPHS=0 runs every step eagerly; so does a run with
+  // profiling on or on the null stream, which cannot be captured)
   bool use_graphs = !c->prof.on && s != nullptr && !noalloc;
   if (const char* e = std::getenv("WTD_DAVIDSON_GRAPHS")) use_graphs = use_graphs && std::atoi(e) != 0;
-  double* gx = use_graphs ? w.alloc((size_t)nb * n) : nullptr;
-  double* gt = use_graphs ? w.alloc((size_t)nb * n) : nullptr;
-  int napply = 0;
-  auto apply_block = [&](int k, const double* X, double* T) {
-    if (!use_graphs || napply++ == 0) {
-      apply_transition_any(c, k, X, T, tda_mask(c));
+  auto run_step = [&](int m, int na, int kprev) {
+    if (!use_graphs) {
+      step(m, na, kprev);
       return;
     }
-    auto it = graphs.ex.find(k);
+    const int key = (m * 512 + na) * 512 + kprev;
+    auto it = graphs.ex.find(key);
     if (it == graphs.ex.end()) {
       hipGraph_t gr = nullptr;
       hipGraphExec_t ge = nullptr;
       WTD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       try {
-        apply_transition_any(c, k, gx, gt, tda_mask(c));
+        step(m, na, kprev);
       } catch (...) {
         (void)hipStreamEndCapture(s, &gr);
         if (gr) (void)hipGraphDestroy(gr);
@@ -1277,52 +1313,67 @@ wtd_status davidson_impl(wtd_ctx* c, int nroots, int nb, double tol, int max_ite
       const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
       WTD_HIP(ie);
-      it = graphs.ex.emplace(k, ge).first;
+      it = graphs.ex.emplace(key, ge).first;
     }
-    WTD_HIP(hipMemcpyAsync(gx, X, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
     WTD_HIP(hipGraphLaunch(it->second, s));
-    WTD_HIP(hipMemcpyAsync(T, gt, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   };
 
-  int added = orthonormalise_append(nb);
-  WTD_REQUIRE(added > 0, WTD_ERR_ARG, "Davidson guess block is rank deficient");
-  apply_block(added, V, W);
-  m = added;
+  std::vector<double> h_th(max_sub), h_rn2(nb), h_rn(nb);
+  std::vector<int> h_ok(max_sub);
+  {
+    // an active list that is never read past its filled entries; zero it once
+    std::vector<int> zeros(max_sub, 0);
+    h2d(c, active, zeros.data(), zeros.size() * sizeof(int));
+  }
+  // read the Ritz values and residual norms of k roots and the flags of basis
+  // rows [f0, f1)
+  auto read_back = [&](int k, int f0, int f1) {
+    WTD_HIP(hipMemcpyAsync(h_th.data(), evals, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipMemcpyAsync(h_rn2.data(), rn2, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (f1 > f0)
+      WTD_HIP(hipMemcpyAsync(h_ok.data() + f0, ok + f0, (f1 - f0) * sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    WTD_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) h_rn[j] = std::sqrt(std::max(h_rn2[j], 0.0));
+    int kept = 0;
+    for (int j = f0; j < f1; ++j) kept += h_ok[j] != 0;
+    return kept;
+  };
+
+  // first iteration: the guess block (eager: its apply forms the pair potentials)
+  ortho_block(0, nb);
+  apply_transition_any(c, nb, V, W, tda_mask(c));
+  finish(nb);
+  int m = nb;
+  int kcur = std::min(nb, m);
+  const int kept0 = read_back(kcur, 0, nb);
+  WTD_REQUIRE(kept0 > 0, WTD_ERR_ARG, "Davidson guess block is rank deficient");
   int it = 0;
   bool converged = false;
-  int kcur = 0;
   for (it = 1; it <= max_iter; ++it) {
-    launch_gram(V, m, W, m, n, H, max_sub, s);
-    launch_jacobi_eig(H, m, max_sub, evals, evecs, s);
-    const int k = std::min(nb, m);
-    kcur = k;
-    launch_lincomb(V, m, n, evecs, m, k, Xr, s);
-    launch_lincomb(W, m, n, evecs, m, k, WY, s);
-    launch_residual(WY, Xr, evals, k, n, Rr, rn2, s);
-    WTD_HIP(hipMemcpyAsync(h_th.data(), evals, k * sizeof(double), hipMemcpyDeviceToHost, s));
-    WTD_HIP(hipMemcpyAsync(h_rn.data(), rn2, k * sizeof(double), hipMemcpyDeviceToHost, s));
-    WTD_HIP(hipStreamSynchronize(s));
-    for (int j = 0; j < k; ++j) h_rn[j] = std::sqrt(std::max(h_rn[j], 0.0));
-    converged = true;
-    for (int j = 0; j < std::min(nroots, k); ++j)
-      if (!(h_rn[j] <= tol)) converged = false;
     if (!std::isfinite(h_th[0])) throw StatusError{WTD_ERR_NONFINITE, "non-finite Ritz value"};
-    if (converged) break;
-    std::vector<int> act;
-    for (int j = 0; j < k; ++j)
-      if (h_rn[j] > tol) act.push_back(j);
-    h2d(c, active, act.data(), act.size() * sizeof(int));
-    launch_precondition(Rr, evals, c->diag, (int)act.size(), n, active, Tc, s);
-    if (m + (int)act.size() > max_sub) {
+    // the same test on the same squared norms as the device's active list
+    converged = true;
+    for (int j = 0; j < std::min(nroots, kcur); ++j)
+      if (!(h_rn2[j] <= tol2)) converged = false;
+    if (converged || it == max_iter) break;
+    int na = 0;
+    for (int j = 0; j < kcur; ++j)
+      if (h_rn2[j] > tol2) ++na;
+    if (na == 0) throw StatusError{WTD_ERR_NONFINITE, "non-finite residual norm"};
+    if (m + na > max_sub) {
       // restart from the current Ritz vectors
-      WTD_HIP(hipMemcpyAsync(V, Xr, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      WTD_HIP(hipMemcpyAsync(W, WY, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      m = k;
+      WTD_HIP(hipMemcpyAsync(V, Xr, (size_t)kcur * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      WTD_HIP(hipMemcpyAsync(W, WY, (size_t)kcur * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      std::vector<int> ones(kcur, 1);
+      h2d(c, ok, ones.data(), ones.size() * sizeof(int));
+      m = kcur;
     }
-    const int na = orthonormalise_append((int)act.size());
-    if (na == 0) break;
-    apply_block(na, V + (int64_t)m * n, W + (int64_t)m * n);
+    run_step(m, na, kcur);
+    const int kept = read_back(std::min(nb, m + na), m, m + na);
     m += na;
+    kcur = std::min(nb, m);
+    if (kept == 0) break;  // every correction lies in the basis: it is exhausted
   }
   const int nr_out = std::min(nroots, kcur);
   for (int j = 0; j < nroots; ++j) {

@@ -270,6 +270,70 @@ k_jacobi(double* __restrict__ A, int m, int ld, double* __restrict__ Vv,
   }
 }
 
+// indices j < k with rnorm2[j] > tol2, in order (the roots that still get a
+// correction; the host applies the same test to the same values); one thread
+__global__ void k_active_list(const double* __restrict__ rnorm2, int k, double tol2,
+                              int* __restrict__ active) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int c = 0;
+  for (int j = 0; j < k; ++j)
+    if (rnorm2[j] > tol2) active[c++] = j;
+}
+
+__global__ void k_sub_rows(double* __restrict__ t, const double* __restrict__ d, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) t[i] -= d[i];
+}
+
+// Normalise row t (length n) or, if its norm is below 1e-10 (the correction
+// lies in the span of the basis), zero it; ok[slot] records which.
+__global__ void __launch_bounds__(kRed)
+k_normalise_or_drop(double* __restrict__ t, int64_t n, int* __restrict__ ok, int slot) {
+  __shared__ double sh[kRed];
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) s += t[r] * t[r];
+  s = block_sum(s, sh);
+  const double nrm = sqrt(s);
+  const bool keep = nrm >= 1e-10;
+  const double f = keep ? 1.0 / nrm : 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) t[r] *= f;
+  if (threadIdx.x == 0) ok[slot] = keep ? 1 : 0;
+}
+
+// Basis slots holding a dropped (zero) correction have zero rows and columns
+// in the subspace matrix; their diagonal is set to 2 g + 1, g the largest
+// absolute row sum of the kept slots (a Gershgorin bound on its eigenvalues),
+// so their Ritz values sort after every Ritz value of the kept basis without
+// changing the scale of the matrix.  One workgroup.
+__global__ void __launch_bounds__(kRed)
+k_fix_dropped(double* __restrict__ H, int ld, const int* __restrict__ ok, int m) {
+  __shared__ double sh[kRed];
+  double g = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    if (!ok[i]) continue;
+    double r = 0.0;
+    for (int j = 0; j < m; ++j) r += fabs(H[(int64_t)i * ld + j]);
+    g = fmax(g, r);
+  }
+  sh[threadIdx.x] = g;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  const double big = 2.0 * sh[0] + 1.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x)
+    if (!ok[i]) H[(int64_t)i * ld + i] = big;
+}
+
+// out[j][i] = in[i][j] for an r x c row-major matrix
+__global__ void k_transpose(const double* __restrict__ in, int r, int c, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r * c) return;
+  const int i = e / c, j = e % c;
+  out[(int64_t)j * r + i] = in[e];
+}
+
 dim3 rows_grid(int64_t n, int k) { return dim3((unsigned)((n + 255) / 256), (unsigned)k); }
 
 }  // namespace
@@ -348,6 +412,35 @@ void launch_cg_direction(double* p, const double* r, const double* beta, int k, 
 
 void launch_scale_rows(double* t, double f, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_row, rows_grid(n, 1), dim3(256), 0, s, t, f, n);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_active_list(const double* rnorm2, int k, double tol2, int* active, hipStream_t s) {
+  hipLaunchKernelGGL(k_active_list, dim3(1), dim3(64), 0, s, rnorm2, k, tol2, active);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_sub_rows(double* t, const double* d, int64_t total, hipStream_t s) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_sub_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, t, d,
+                     total);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_normalise_or_drop(double* t, int64_t n, int* ok, int slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalise_or_drop, dim3(1), dim3(kRed), 0, s, t, n, ok, slot);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_fix_dropped(double* H, int ld, const int* ok, int m, hipStream_t s) {
+  hipLaunchKernelGGL(k_fix_dropped, dim3(1), dim3(kRed), 0, s, H, ld, ok, m);
+  WTD_HIP(hipGetLastError());
+}
+
+void launch_transpose(const double* in, int r, int c, double* out, hipStream_t s) {
+  if (r * c <= 0) return;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((r * c + 255) / 256)), dim3(256), 0, s, in, r, c,
+                     out);
   WTD_HIP(hipGetLastError());
 }
 

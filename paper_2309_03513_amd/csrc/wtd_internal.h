@@ -202,5 +202,11 @@ void launch_cg_update(double* z, double* r, const double* p, const double* ap,
                       const double* alpha, int k, int64_t n, hipStream_t s);
 void launch_cg_direction(double* p, const double* r, const double* beta, int k, int64_t n,
                          hipStream_t s);
+// device-side pieces of one Davidson step (no host synchronisation)
+void launch_active_list(const double* rnorm2, int k, double tol2, int* active, hipStream_t s);
+void launch_sub_rows(double* t, const double* d, int64_t total, hipStream_t s);
+void launch_normalise_or_drop(double* t, int64_t n, int* ok, int slot, hipStream_t s);
+void launch_fix_dropped(double* H, int ld, const int* ok, int m, hipStream_t s);
+void launch_transpose(const double* in, int r, int c, double* out, hipStream_t s);
 
 }  // namespace wtd

@@ -72,12 +72,15 @@ def test_apply_nocc128_nb16(systems, prec, tol):
 @pytest.mark.parametrize("cfg,prec,tol,ck", [("p6", "fp32", 2e-5, None),
                                              ("p6", "fp64", 1e-10, 0.0),
                                              ("p7", "fp64", 1e-10, None),
-                                             ("p7", "fp32", 2e-5, None)])
+                                             ("p7", "fp32", 2e-5, None),
+                                             ("p8", "fp32", 2e-5, None),
+                                             ("p8", "fp64", 1e-10, None)])
 def test_apply_batch_grids(systems, cfg, prec, tol, ck):
-    """The 96^3 and 60^3 grids of the heterogeneous batch (runtime FFT plans,
-    a radix-5 factor), sampled output rows against the oracle.  FP64 on 96^3
-    runs the spin-flip operator (c_K = 0): the density response does not fit
-    there (next test)."""
+    """The 96^3, 60^3 and 48^3 grids of the heterogeneous batch (a radix-5
+    factor on 60^3; 140 occupied orbitals on 48^3, so the exchange runs
+    row-blocked with a ragged last block), sampled output rows against the
+    oracle.  FP64 on 96^3 runs the spin-flip operator (c_K = 0): the density
+    response does not fit there (next test)."""
     s = systems(cfg) if ck is None else systems(cfg, c_k=ck)
     nb = s.cfg.nb
     a = trials_random(s, nb)
@@ -90,6 +93,22 @@ def test_apply_batch_grids(systems, cfg, prec, tol, ck):
     err = rel_err(got, ref)
     say(f"  rel err {err:.3e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("term", ["K1E", "K1D"])
+def test_apply_48cubed_blocked_terms_fp32(systems, term):
+    """The K terms alone on the 48^3 / Nocc = 140 / Nb = 5 system (sampled
+    rows): they are small next to D, so they are checked on their own."""
+    s = systems("p8")
+    a = trials_random(s, s.cfg.nb)
+    rows = [0, 70, 139]
+    say(f"apply fp32 cfg=p8 term={term} rows={rows}")
+    L = _ctx(s, s.cfg.nb, "fp32", TERMS[term])
+    got = to_complex(L.apply(a))[:, rows]
+    L.close()
+    err = rel_err(got, oracle.apply_liouville(s, a, terms=TERMS[term], rows=rows))
+    say(f"  rel err {err:.3e}")
+    assert err <= 2e-5
 
 
 def test_fp64_96_response_does_not_fit_lds(systems):
