@@ -31,7 +31,7 @@ constexpr int kStickRegs = 6;  // rounds of density-stick loads held in register
 // 72^3 / 40 Ry, 1,305 at 108^3)
 template <int SN>
 constexpr int wave_stick_regs() {
-  return SN == 108 ? 3 : 2;
+  return SN >= 96 ? 3 : 2;
 }
 // (108 x 108 planes run one workgroup per CU, so they keep every round of the
 // 108^3 density sticks in registers)
@@ -982,66 +982,88 @@ void check_lds(size_t bytes) {
 }  // namespace
 
 // ============================================================================ launchers
-// Grid sizes with compile-time FFT plans; other sizes use the runtime plans.
-int static_size(int n) { return (n == 72 || n == 108) ? n : 0; }
+// Grid sizes with compile-time FFT plans (the benchmark's 72 and 108 and the
+// batch's 48, 60 and 96); other sizes use the runtime plans.
+int static_size(int n) {
+  return (n == 48 || n == 60 || n == 72 || n == 96 || n == 108) ? n : 0;
+}
 int plane_static(const Geometry& g) { return g.n1 == g.n2 ? static_size(g.n1) : 0; }
+
+#define WTD_STICK_CASE(N, K, T, grid, lds0, stream, ...)                                     \
+  case N: {                                                                                 \
+    const size_t l_ = (lds0) + N * sizeof(cplx<T>);                                         \
+    set_lds((K<1, N, T>), l_);                                                              \
+    hipLaunchKernelGGL((K<1, N, T>), grid, dim3(kStickThreads), l_, stream, __VA_ARGS__);   \
+  } break;
 
 // Launch a stick kernel K<MB, SN, T> with the right static size or radix bound.
 #define WTD_STICK_LAUNCH(K, T, grid, lds0, stream, ...)                                     \
   do {                                                                                      \
-    const int sn_ = static_size(g.n0);                                                      \
-    if (sn_ == 72) {                                                                        \
-      const size_t l_ = (lds0) + 72 * sizeof(cplx<T>);                                      \
-      set_lds((K<1, 72, T>), l_);                                                           \
-      hipLaunchKernelGGL((K<1, 72, T>), grid, dim3(kStickThreads), l_, stream, __VA_ARGS__); \
-    } else if (sn_ == 108) {                                                                \
-      const size_t l_ = (lds0) + 108 * sizeof(cplx<T>);                                     \
-      set_lds((K<1, 108, T>), l_);                                                          \
-      hipLaunchKernelGGL((K<1, 108, T>), grid, dim3(kStickThreads), l_, stream,             \
-                         __VA_ARGS__);                                                      \
-    } else {                                                                                \
-      const int mb_ = pick_maxb(kStickTile, g.plan0, kStickThreads);                        \
-      WTD_MAXB_DISPATCH(mb_, {                                                              \
-        set_lds((K<MB, 0, T>), (lds0));                                                     \
-        hipLaunchKernelGGL((K<MB, 0, T>), grid, dim3(kStickThreads), (lds0), stream,        \
-                           __VA_ARGS__);                                                    \
-      });                                                                                   \
+    switch (static_size(g.n0)) {                                                            \
+      WTD_STICK_CASE(48, K, T, grid, lds0, stream, __VA_ARGS__)                             \
+      WTD_STICK_CASE(60, K, T, grid, lds0, stream, __VA_ARGS__)                             \
+      WTD_STICK_CASE(72, K, T, grid, lds0, stream, __VA_ARGS__)                             \
+      WTD_STICK_CASE(96, K, T, grid, lds0, stream, __VA_ARGS__)                             \
+      WTD_STICK_CASE(108, K, T, grid, lds0, stream, __VA_ARGS__)                            \
+      default: {                                                                            \
+        const int mb_ = pick_maxb(kStickTile, g.plan0, kStickThreads);                      \
+        WTD_MAXB_DISPATCH(mb_, {                                                            \
+          set_lds((K<MB, 0, T>), (lds0));                                                   \
+          hipLaunchKernelGGL((K<MB, 0, T>), grid, dim3(kStickThreads), (lds0), stream,      \
+                             __VA_ARGS__);                                                  \
+        });                                                                                 \
+      }                                                                                     \
     }                                                                                       \
     WTD_HIP(hipGetLastError());                                                             \
   } while (0)
 
-// Launch a plane kernel K<MB1, MB2, SN, T>.
-#define WTD_PLANE_LAUNCH(K, T, grid, lds0, stream, ...)                                      \
+#define WTD_PLANE_CASE(N, K, T, grid, lds0, stream, ...)                                     \
+  case N: {                                                                                 \
+    const size_t l_ = (lds0) + N * sizeof(cplx<T>);                                         \
+    check_lds(l_);                                                                          \
+    set_lds((K<1, 1, N, T>), l_);                                                           \
+    hipLaunchKernelGGL((K<1, 1, N, T>), grid, dim3(kPlaneThreads), l_, stream, __VA_ARGS__); \
+  } break;
+
+// Launch a plane kernel K<MB1, MB2, SN, T> with the compile-time plan of size
+// SN_ (0: runtime plans).
+#define WTD_PLANE_LAUNCH_SN(SN_, K, T, grid, lds0, stream, ...)                              \
   do {                                                                                       \
-    const int sn_ = plane_static(g);                                                         \
-    if (sn_ == 72) {                                                                         \
-      const size_t l_ = (lds0) + 72 * sizeof(cplx<T>);                                       \
-      check_lds(l_);                                                                         \
-      set_lds((K<1, 1, 72, T>), l_);                                                         \
-      hipLaunchKernelGGL((K<1, 1, 72, T>), grid, dim3(kPlaneThreads), l_, stream,            \
-                         __VA_ARGS__);                                                       \
-    } else if (sn_ == 108) {                                                                 \
-      const size_t l_ = (lds0) + 108 * sizeof(cplx<T>);                                      \
-      check_lds(l_);                                                                         \
-      set_lds((K<1, 1, 108, T>), l_);                                                        \
-      hipLaunchKernelGGL((K<1, 1, 108, T>), grid, dim3(kPlaneThreads), l_, stream,           \
-                         __VA_ARGS__);                                                       \
-    } else {                                                                                 \
-      check_lds(lds0);                                                                       \
-      const int mb1_ = pick_maxb(g.n2, g.plan1, kPlaneThreads);                              \
-      const int mb2_ = pick_maxb(g.n1, g.plan2, kPlaneThreads);                              \
-      WTD_MAXB_DISPATCH(mb1_, {                                                              \
-        constexpr int M1 = MB;                                                               \
-        WTD_MAXB_DISPATCH(mb2_, {                                                            \
-          constexpr int M2 = MB;                                                             \
-          set_lds((K<M1, M2, 0, T>), (lds0));                                                \
-          hipLaunchKernelGGL((K<M1, M2, 0, T>), grid, dim3(kPlaneThreads), (lds0), stream,   \
-                             __VA_ARGS__);                                                   \
+    switch (SN_) {                                                                           \
+      WTD_PLANE_CASE(48, K, T, grid, lds0, stream, __VA_ARGS__)                              \
+      WTD_PLANE_CASE(60, K, T, grid, lds0, stream, __VA_ARGS__)                              \
+      WTD_PLANE_CASE(72, K, T, grid, lds0, stream, __VA_ARGS__)                              \
+      WTD_PLANE_CASE(96, K, T, grid, lds0, stream, __VA_ARGS__)                              \
+      WTD_PLANE_CASE(108, K, T, grid, lds0, stream, __VA_ARGS__)                             \
+      default: {                                                                             \
+        check_lds(lds0);                                                                     \
+        const int mb1_ = pick_maxb(g.n2, g.plan1, kPlaneThreads);                            \
+        const int mb2_ = pick_maxb(g.n1, g.plan2, kPlaneThreads);                            \
+        WTD_MAXB_DISPATCH(mb1_, {                                                            \
+          constexpr int M1 = MB;                                                             \
+          WTD_MAXB_DISPATCH(mb2_, {                                                          \
+            constexpr int M2 = MB;                                                           \
+            set_lds((K<M1, M2, 0, T>), (lds0));                                              \
+            hipLaunchKernelGGL((K<M1, M2, 0, T>), grid, dim3(kPlaneThreads), (lds0), stream, \
+                               __VA_ARGS__);                                                 \
+          });                                                                                \
         });                                                                                  \
-      });                                                                                    \
+      }                                                                                      \
     }                                                                                        \
     WTD_HIP(hipGetLastError());                                                              \
   } while (0)
+
+#define WTD_PLANE_LAUNCH(K, T, grid, lds0, stream, ...) \
+  WTD_PLANE_LAUNCH_SN(plane_static(g), K, T, grid, lds0, stream, __VA_ARGS__)
+
+// static size for the wave-stick plane kernels, which keep the wave sticks of
+// an item in wave_stick_regs<SN>() registers per thread (runtime plans where
+// the sphere has more sticks than that holds)
+int plane_static_wave(const Geometry& g) {
+  const int sn = plane_static(g);
+  const int ws = sn >= 96 ? 3 : 2;
+  return (sn > 0 && g.nw <= ws * kPlaneThreads) ? sn : 0;
+}
 
 template <typename T>
 void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
@@ -1062,13 +1084,11 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   const int npt = (per_trial + 1) / 2;
   if (!drho || !part) ngroup = 1;
   ngroup = std::max(1, std::min(ngroup, npt));
-  WTD_REQUIRE((plane_static(g) != 72 || g.nw <= wave_stick_regs<72>() * kPlaneThreads) &&
-                  (plane_static(g) != 108 || g.nw <= wave_stick_regs<108>() * kPlaneThreads),
-              WTD_ERR_SHAPE, "too many wave sticks for the compile-time plane kernel");
   dim3 grid((unsigned)((g.n0 * nb * ngroup + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
   T* dtarget = (ngroup > 1) ? part : drho;
-  WTD_PLANE_LAUNCH(k_wsticks_to_fields, T, grid, lds, s, wst, npt, per_trial, g.n0, g.n1, g.n2,
+  WTD_PLANE_LAUNCH_SN(plane_static_wave(g), k_wsticks_to_fields, T, grid, lds, s, wst, npt,
+                      per_trial, g.n0, g.n1, g.n2,
                    g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), scale, out, phi, dtarget, ngroup, nb);
   if (ngroup > 1) {
