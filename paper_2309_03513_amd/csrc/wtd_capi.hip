@@ -505,14 +505,17 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
     WTD_HIP(hipMemsetAsync(c->fxc, 0, nr * sizeof(T), s));
   }
 
-  // the trial transform that forms the density response keeps a grid plane and
-  // its real accumulator in LDS
-  if ((c->mask & (WTD_TERM_K1E | WTD_TERM_K2E)) && c->ck != 0.0)
-    WTD_REQUIRE((size_t)c->g.plane * (sizeof(cplx<T>) + sizeof(T)) + 108 * sizeof(cplx<T>) <=
-                    160 * 1024,
+  // the trial transform that forms the density response keeps a grid plane in
+  // LDS, and with runtime FFT plans also its real accumulator
+  if ((c->mask & (WTD_TERM_K1E | WTD_TERM_K2E)) && c->ck != 0.0) {
+    const bool reg_acc = plane_static_wave(c->g) > 0;
+    WTD_REQUIRE((size_t)c->g.plane * (sizeof(cplx<T>) + (reg_acc ? 0 : sizeof(T))) +
+                        108 * sizeof(cplx<T>) <= 160 * 1024,
                 WTD_ERR_SHAPE,
-                "the density response needs a grid plane and its accumulator in 160 KB of LDS "
-                "(FP64: planes up to about 80 x 80; FP32: up to about 114 x 114)");
+                "the density response needs a grid plane (and, with runtime FFT plans, its "
+                "accumulator) in 160 KB of LDS (FP64: planes up to 96 x 96 with compile-time "
+                "plans, about 80 x 80 otherwise; FP32: up to 108 x 108)");
+  }
   // pairs v <= v' (row-major), packed two per complex transform
   c->npairs = nocc * (nocc + 1) / 2;
   c->npack_pairs = (c->npairs + 1) / 2;

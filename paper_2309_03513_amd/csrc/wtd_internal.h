@@ -62,6 +62,8 @@ constexpr int kStickTile = 16;
 
 // ----------------------------------------------------------------------------
 // Kernel launchers (wtd_transforms.hip)
+// compile-time plane size of the wave-stick plane kernels (0: runtime plans)
+int plane_static_wave(const Geometry& g);
 template <typename T>
 void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
                               int per_trial, cplx<T>* wst, hipStream_t s);

@@ -185,8 +185,10 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   extern __shared__ unsigned char smem_raw[];
   const int plane = n1 * n2;
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  // the density accumulator: in LDS behind the plane for runtime plans, in
+  // registers (each thread always owns the same points) for compile-time ones
   T* acc = reinterpret_cast<T*>(pl + plane);
-  cplx<T>* twl = reinterpret_cast<cplx<T>*>(acc + (drho ? plane : 0));
+  cplx<T>* twl = reinterpret_cast<cplx<T>*>(acc + ((drho && SN == 0) ? plane : 0));
   // item = (i0, group, b), b fastest: the trials of one (plane, orbital group)
   // read the same orbital planes and run back to back on one XCD.  The packs
   // of trial b are split into ngroup contiguous groups; each group writes its
@@ -201,14 +203,15 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
   const int j0 = grp * per, j1 = min(npt, j0 + per);
   const int64_t nr = (int64_t)n0 * plane;
   const int64_t poff = (int64_t)i0 * plane;
-  if (drho)
-    for (int i = threadIdx.x; i < plane; i += blockDim.x) acc[i] = T(0);
   if constexpr (SN > 0) {
     // the next pack's sticks and the current pack's orbital planes are loaded
     // into registers before the plane FFT, so their latency overlaps it
     constexpr int PL = SN * SN;
     constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
     constexpr int WS = wave_stick_regs<SN>();  // nw <= WS * kPlaneThreads, host-checked
+    T racc[EL];
+#pragma unroll
+    for (int e = 0; e < EL; ++e) racc[e] = T(0);
     cplx<T> sv[WS];
     int kv[WS];
 #pragma unroll
@@ -255,12 +258,22 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
           const T a = z.x * scale, c = z.y * scale;
           o1[i] = a;
           if (has2) o2[i] = c;
-          if (drho) acc[i] += f1[e] * a + f2[e] * c;
+          if (drho) racc[e] += f1[e] * a + f2[e] * c;
         }
       }
       __syncthreads();
     }
+    if (drho) {
+      T* d = drho + ((int64_t)grp * nbtot + b) * nr + poff;
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) d[i] = racc[e];
+      }
+    }
   } else {
+  if (drho)
+    for (int i = threadIdx.x; i < plane; i += blockDim.x) acc[i] = T(0);
   for (int j = j0; j < j1; ++j) {
     const int pack = b * npt + j;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) pl[i] = {T(0), T(0)};
@@ -286,10 +299,10 @@ k_wsticks_to_fields(const cplx<T>* __restrict__ wst, int npt, int per_trial, int
     }
     __syncthreads();
   }
-  }
   if (drho) {
     T* d = drho + ((int64_t)grp * nbtot + b) * nr + poff;
     for (int i = threadIdx.x; i < plane; i += blockDim.x) d[i] = acc[i];
+  }
   }
 }
 
@@ -1085,9 +1098,11 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   if (!drho || !part) ngroup = 1;
   ngroup = std::max(1, std::min(ngroup, npt));
   dim3 grid((unsigned)((g.n0 * nb * ngroup + 7) / 8 * 8));
-  const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho ? sizeof(T) : 0));
+  const int sn = plane_static_wave(g);
+  // compile-time plans accumulate the density in registers, runtime plans in LDS
+  const size_t lds = (size_t)g.plane * (sizeof(cplx<T>) + (drho && sn == 0 ? sizeof(T) : 0));
   T* dtarget = (ngroup > 1) ? part : drho;
-  WTD_PLANE_LAUNCH_SN(plane_static_wave(g), k_wsticks_to_fields, T, grid, lds, s, wst, npt,
+  WTD_PLANE_LAUNCH_SN(sn, k_wsticks_to_fields, T, grid, lds, s, wst, npt,
                       per_trial, g.n0, g.n1, g.n2,
                    g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), scale, out, phi, dtarget, ngroup, nb);

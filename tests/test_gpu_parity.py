@@ -79,8 +79,8 @@ def test_apply_batch_grids(systems, cfg, prec, tol, ck):
     """The 96^3, 60^3 and 48^3 grids of the heterogeneous batch (a radix-5
     factor on 60^3; 140 occupied orbitals on 48^3, so the exchange runs
     row-blocked with a ragged last block), sampled output rows against the
-    oracle.  FP64 on 96^3 runs the spin-flip operator (c_K = 0): the density
-    response does not fit there (next test)."""
+    oracle (FP64 on 96^3 with c_K = 0, the spin-flip operator; with the
+    density response in the next test)."""
     s = systems(cfg) if ck is None else systems(cfg, c_k=ck)
     nb = s.cfg.nb
     a = trials_random(s, nb)
@@ -111,16 +111,21 @@ def test_apply_48cubed_blocked_terms_fp32(systems, term):
     assert err <= 2e-5
 
 
-def test_fp64_96_response_does_not_fit_lds(systems):
-    """A 96 x 96 FP64 plane and its density accumulator (221 KB) exceed the
-    160 KB of LDS: context creation with the response term reports
-    WTD_ERR_SHAPE instead of failing at the first apply."""
-    from paper_2309_03513_amd import WtdError
+@pytest.mark.parametrize("term", ["K1E", "ALL"])
+def test_fp64_96_with_response(systems, term):
+    """FP64 on the 96^3 grid with the density response: the 96 x 96 FP64 plane
+    (147 KB) fits in LDS and the compile-time-plan trial transform keeps the
+    density accumulator in registers."""
     s = systems("p6")
-    say("p6 fp64 context creation with the response term (expected shape error)")
-    with pytest.raises(WtdError) as e:
-        _ctx(s, 1, "fp64")
-    assert e.value.status == -2
+    a = trials_random(s, s.cfg.nb)
+    rows = [0, s.nocc // 2, s.nocc - 1]
+    say(f"apply fp64 cfg=p6 (96^3) term={term} rows={rows}")
+    L = _ctx(s, s.cfg.nb, "fp64", TERMS[term])
+    got = to_complex(L.apply(a))[:, rows]
+    L.close()
+    err = rel_err(got, oracle.apply_liouville(s, a, terms=TERMS[term], rows=rows))
+    say(f"  rel err {err:.3e}")
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("cfg", ["c1", "p1", "p3"])
