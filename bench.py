@@ -301,6 +301,34 @@ def accuracy_fp32(s, nb, nroots):
             "reference": "oracle FP64 block Davidson, tests/golden/roots_c2.json"}
 
 
+def roots_fp32_vs_fp64(cfg, nb64):
+    """Davidson roots of one system in FP32 bulk (block of cfg.nb) and in FP64
+    (block of nb64; the 108^3 / Nocc = 432 FP64 context holds 16 trial fields
+    at a time in HBM), the FP32 roots against the FP64 ones in meV.  The FP64
+    GPU apply is pinned to the oracle by sampled rows (tests/test_gpu_c3.py)."""
+    from gen import make_system
+    from paper_2309_03513_amd import Liouville
+    s = make_system(cfg)
+    out = {"workload": f"{cfg.name}: {s.n[0]}^3 grid, Nocc={s.nocc}, c_K={cfg.c_k}",
+           "nroots": cfg.nroots}
+    roots = {}
+    for prec, nb, tol in (("fp64", nb64, 1e-7), ("fp32", cfg.nb, 1e-5)):
+        L = Liouville(s, max_nb=nb, precision=prec)
+        t0 = time.perf_counter()
+        om, _, res, nit, st = L.davidson(cfg.nroots, nb, tol=tol, max_iter=200, want_x=False)
+        t = time.perf_counter() - t0
+        L.close()
+        roots[prec] = np.asarray(om)
+        out[prec] = {"block": nb, "tol": tol, "iterations": int(nit), "seconds": t,
+                     "status": int(st), "max_residual": float(np.max(res)),
+                     "roots_hartree": [float(x) for x in om]}
+        log(f"{cfg.name} {prec} davidson: nb={nb}, {nit} iterations, {t:.1f} s, status {st}")
+    d = np.abs(roots["fp32"] - roots["fp64"]) / MEV
+    out["max_abs_domega_meV"] = float(d.max())
+    log(f"{cfg.name}: FP32 roots vs FP64 roots: max |d omega| = {d.max():.4f} meV")
+    return out
+
+
 def cpu_baseline(s, nb, a_np, single_rows=(0, 1, 2)):
     """Time the oracle on the same block: one whole block on every host core
     (the value), and a single-core figure extrapolated from a row sample.
@@ -366,6 +394,9 @@ def main():
                     help="timed applies of the full Z-vector operator (0: skip)")
     ap.add_argument("--no-cached", action="store_true",
                     help="skip the extra timing with the pair potentials kept between applies")
+    ap.add_argument("--roots", action="store_true",
+                    help="only compare the FP32 Davidson roots of the workload with its FP64 "
+                         "roots (FP64 block of 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -394,6 +425,9 @@ def main():
     if args.ck is not None:
         import dataclasses
         cfg = dataclasses.replace(cfg, c_k=args.ck)
+    if args.roots:
+        print(json.dumps(roots_fp32_vs_fp64(cfg, min(16, cfg.nb))), flush=True)
+        return
     nb = cfg.nb
     log(f"building system {cfg.name}")
     s = make_system(cfg)

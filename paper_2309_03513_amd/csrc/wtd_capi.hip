@@ -426,6 +426,34 @@ void build_geometry(wtd_ctx* c, const wtd_system* sys) {
   int* d_dk = (int*)dalloc(c, dk12.size() * sizeof(int));
   upload(c, d_dk, dk12);
   g.dst_k12 = d_dk;
+  // rows of the stick sets for the register-quad plane kernels
+  auto stick_rows = [&](const std::vector<int>& k12, int& nrow, const int4*& dev) {
+    std::vector<int4> rows;
+    bool regular = true;
+    const int ns = (int)k12.size();
+    for (int s0 = 0; s0 < ns;) {
+      const int k1 = k12[s0] / n[2];
+      int s1 = s0;
+      while (s1 < ns && k12[s1] / n[2] == k1) ++s1;
+      const int cnt = s1 - s0, R = (cnt - 1) / 2;
+      bool ok = cnt % 2 == 1 && 2 * R + 1 <= n[2];
+      for (int i = 0; ok && i < cnt; ++i)
+        ok = k12[s0 + i] % n[2] == (i <= R ? i : n[2] - (cnt - i));
+      regular = regular && ok;
+      rows.push_back(int4{k1, s0, R, 0});
+      s0 = s1;
+    }
+    nrow = regular ? (int)rows.size() : 0;
+    int4* d = (int4*)dalloc(c, std::max<size_t>(rows.size(), 1) * sizeof(int4));
+    if (!rows.empty()) h2d(c, d, rows.data(), rows.size() * sizeof(int4));
+    dev = d;
+  };
+  stick_rows(dk12, g.ndrow, g.drows);
+  stick_rows(wk12, g.nwrow, g.wrows);
+  {
+    const char* e = std::getenv("WTD_QUAD_PLANES");
+    g.quad_sn = quad_plane_size(g, sizeof(T), e && std::atoi(e) != 0);
+  }
   std::vector<T> kern((size_t)g.nd * g.n0);
   for (int s = 0; s < g.nd; ++s) {
     const int m1 = unfold(dk12[s] / n[2], n[1]), m2 = unfold(dk12[s] % n[2], n[2]);
@@ -507,7 +535,7 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
 
   // the trial transform that forms the density response keeps a grid plane in
   // LDS, and with runtime FFT plans also its real accumulator
-  if ((c->mask & (WTD_TERM_K1E | WTD_TERM_K2E)) && c->ck != 0.0) {
+  if ((c->mask & (WTD_TERM_K1E | WTD_TERM_K2E)) && c->ck != 0.0 && c->g.quad_sn == 0) {
     const bool reg_acc = plane_static_wave(c->g) > 0;
     WTD_REQUIRE((size_t)c->g.plane * (sizeof(cplx<T>) + (reg_acc ? 0 : sizeof(T))) +
                         108 * sizeof(cplx<T>) <= 160 * 1024,

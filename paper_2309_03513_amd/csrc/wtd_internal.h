@@ -56,6 +56,14 @@ struct Geometry {
   int nds;                // stick row stride of density-stick buffers (nd rounded up to 16)
   const int* dst_k12;     // [nd]
   const void* dkern;      // [nd][n0] Coulomb kernel / N_r, working precision
+  // rows k1 of the density and wave stick sets: (k1, first stick, R, 0), the
+  // row holding k2 = 0..R and n2 - R..n2 - 1 (0 rows: not of that form)
+  int ndrow, nwrow;
+  const int4* drows;
+  const int4* wrows;
+  // plane size of the register-quad plane kernels, used where the complex plane
+  // does not fit in LDS (0: the LDS plane kernels)
+  int quad_sn;
 };
 
 constexpr int kStickTile = 16;
@@ -64,6 +72,9 @@ constexpr int kStickTile = 16;
 // Kernel launchers (wtd_transforms.hip)
 // compile-time plane size of the wave-stick plane kernels (0: runtime plans)
 int plane_static_wave(const Geometry& g);
+// plane size for the register-quad plane kernels of a context of element size
+// `elem` (0: none); force takes them wherever they apply (a test hook)
+int quad_plane_size(const Geometry& g, size_t elem, bool force);
 template <typename T>
 void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
                               int per_trial, cplx<T>* wst, hipStream_t s);

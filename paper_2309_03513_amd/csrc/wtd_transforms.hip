@@ -17,6 +17,7 @@
 #include <algorithm>
 
 #include "wtd_fft_ct.h"
+#include "wtd_fft_reg.h"
 #include "wtd_internal.h"
 
 namespace wtd {
@@ -477,6 +478,267 @@ k_pairs_to_dsticks(const T* __restrict__ src, const int4* __restrict__ quads, in
       __syncthreads();
       plane_fft<-1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
       for (int st = threadIdx.x; st < nd; st += blockDim.x) o[st] = pl[k12[st]];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- register-quad plane kernels
+// For planes whose complex field does not fit in LDS (FP64 108 x 108): each
+// line of SN points is held by a quad of lanes with SN / 4 points each
+// (fft_quad_*), so the 2D FFT needs LDS only for the transpose between the row
+// and the column transforms, restricted to the rows k1 that the stick set
+// occupies.  rows[r] = (k1, first stick, R, 0): row r holds k2 = 0..R and
+// SN - R..SN - 1 (sticks ordered by k1, then k2).  One (plane, pack) item per
+// workgroup of quad_threads(SN) threads, quad qd = threadIdx / 4.
+constexpr int quad_threads(int sn) { return (4 * sn + 63) / 64 * 64; }
+
+// position of k2 within a stick row of half-width R, or -1
+__device__ __forceinline__ int row_pos(int k2, int R, int sn) {
+  return k2 <= R ? k2 : (k2 >= sn - R ? k2 - (sn - 2 * R - 1) : -1);
+}
+
+// rowof[k1] = stick row of k1, or -1 (callers synchronise before use)
+template <int SN>
+__device__ __forceinline__ void fill_rowof(int* rowof, const int4* __restrict__ rows, int nrow) {
+  for (int k = threadIdx.x; k < SN; k += blockDim.x) rowof[k] = -1;
+  __syncthreads();
+  for (int r = threadIdx.x; r < nrow; r += blockDim.x) rowof[rows[r].x] = r;
+}
+
+// pair products -> density sticks: columns (along i1) straight from the
+// orbital planes, the stick rows through LDS, then the rows (along i2)
+template <int SN, typename T>
+__global__ void __launch_bounds__(quad_threads(SN))
+k_pairs_to_dsticks_q(const T* __restrict__ src, const int4* __restrict__ quads, int npack,
+                     int limit, int n0, int nds, int nrow, const int4* __restrict__ rows,
+                     cplx<T>* __restrict__ dst) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int M = SN / 4, TS = SN + 1, PL = SN * SN;
+  cplx<T>* tr = reinterpret_cast<cplx<T>*>(smem_raw);  // [nrow][TS]
+  int* rowof = reinterpret_cast<int*>(tr + nrow * TS);
+  const int item = xcd_item(n0 * npack);
+  if (item < 0) return;
+  const int i0 = item / npack;
+  const int pack = item - i0 * npack;
+  fill_rowof<SN>(rowof, rows, nrow);
+  __syncthreads();
+  const int qd = threadIdx.x >> 2, e = threadIdx.x & 3, qb = quad_block(e);
+  const int64_t nr = (int64_t)n0 * PL;
+  int4 q = quads[pack];
+  if (q.z >= limit) q.z = -1;  // packs past the last valid field carry no imaginary part
+  if (qd < SN) {
+    // column i2 = qd, points i1 = e M .. e M + M - 1; missing factors read the
+    // first field again and are replaced by 1 (or the imaginary part by 0)
+    const int64_t off = (int64_t)i0 * PL + (int64_t)(e * M) * SN + qd;
+    const bool hb = q.y >= 0, hc = q.z >= 0, hd = q.z >= 0 && q.w >= 0;
+    const T* fa = src + (int64_t)q.x * nr + off;
+    const T* fb = src + (int64_t)(hb ? q.y : q.x) * nr + off;
+    const T* fc = src + (int64_t)(hc ? q.z : q.x) * nr + off;
+    const T* fd = src + (int64_t)(hd ? q.w : q.x) * nr + off;
+    cplx<T> x[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const T a = fa[m * SN], bb = fb[m * SN];
+      x[m].x = hb ? a * bb : a;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const T c = fc[m * SN], d = fd[m * SN];
+      x[m].y = hc ? (hd ? c * d : c) : T(0);
+    }
+    fft_quad_fwd_contig<SN>(x, e);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int r = rowof[4 * k + qb];
+      if (r >= 0) tr[r * TS + qd] = x[k];
+    }
+  }
+  __syncthreads();
+  if (qd < nrow) {
+    cplx<T> x[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] = tr[qd * TS + e * M + m];
+    fft_quad_fwd_contig<SN>(x, e);
+    const int4 rw = rows[qd];
+    cplx<T>* o = dst + ((int64_t)pack * n0 + i0) * nds + rw.y;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int p = row_pos(4 * k + qb, rw.z, SN);
+      if (p >= 0) o[p] = x[k];
+    }
+  }
+}
+
+// inverse 2D FFT of a pack of sticks: the stick rows (along k2) into LDS, then
+// the columns (along k1); the lanes of column i2 hold points i1 = e M + m
+template <int SN, typename T>
+__device__ __forceinline__ void quad_plane_inverse(const cplx<T>* __restrict__ src, int nrow,
+                                                   const int4* __restrict__ rows,
+                                                   const int* rowof, cplx<T>* tr,
+                                                   cplx<T> (&x)[SN / 4]) {
+  constexpr int M = SN / 4, TS = SN + 1;
+  const int qd = threadIdx.x >> 2, e = threadIdx.x & 3, qb = quad_block(e);
+  if (qd < nrow) {
+    const int4 rw = rows[qd];
+    cplx<T> y[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int p = row_pos(4 * k + qb, rw.z, SN);
+      y[k] = p >= 0 ? src[rw.y + p] : cplx<T>{T(0), T(0)};
+    }
+    fft_quad_inv_contig<SN>(y, e);
+#pragma unroll
+    for (int m = 0; m < M; ++m) tr[qd * TS + e * M + m] = y[m];
+  }
+  __syncthreads();
+  if (qd < SN) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int r = rowof[4 * k + qb];
+      x[k] = r >= 0 ? tr[r * TS + qd] : cplx<T>{T(0), T(0)};
+    }
+    fft_quad_inv_contig<SN>(x, e);
+  }
+}
+
+// density sticks -> real fields (fields 2 pack and 2 pack + 1, [field][N_r])
+template <int SN, typename T>
+__global__ void __launch_bounds__(quad_threads(SN))
+k_dsticks_to_fields_q(const cplx<T>* __restrict__ dst, int npack, int nfield, int n0, int nds,
+                      int nrow, const int4* __restrict__ rows, T* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int M = SN / 4, TS = SN + 1, PL = SN * SN;
+  cplx<T>* tr = reinterpret_cast<cplx<T>*>(smem_raw);
+  int* rowof = reinterpret_cast<int*>(tr + nrow * TS);
+  const int item = xcd_item(n0 * npack);
+  if (item < 0) return;
+  const int i0 = item / npack;
+  const int pack = item - i0 * npack;
+  fill_rowof<SN>(rowof, rows, nrow);
+  __syncthreads();
+  const int qd = threadIdx.x >> 2, e = threadIdx.x & 3;
+  cplx<T> x[M];
+  quad_plane_inverse<SN>(dst + ((int64_t)pack * n0 + i0) * nds, nrow, rows, rowof, tr, x);
+  if (qd < SN) {
+    const int64_t nr = (int64_t)n0 * PL;
+    T* o1 = out + (int64_t)(2 * pack) * nr + (int64_t)i0 * PL + (int64_t)(e * M) * SN + qd;
+    const bool has2 = 2 * pack + 1 < nfield;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      o1[m * SN] = x[m].x;
+      if (has2) o1[nr + m * SN] = x[m].y;
+    }
+  }
+}
+
+// wave sticks -> real fields of the trial block, with the density response
+// drho_b = sum_v phi_v out_bv accumulated in registers (each lane owns the same
+// points for every pack); items (i0, group, b) as k_wsticks_to_fields
+template <int SN, typename T>
+__global__ void __launch_bounds__(quad_threads(SN))
+k_wsticks_to_fields_q(const cplx<T>* __restrict__ wst, int npt, int per_trial, int n0, int nws,
+                      int nrow, const int4* __restrict__ rows, T scale, T* __restrict__ out,
+                      const T* __restrict__ phi, T* __restrict__ drho, int ngroup, int nbtot) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int M = SN / 4, TS = SN + 1, PL = SN * SN;
+  cplx<T>* tr = reinterpret_cast<cplx<T>*>(smem_raw);
+  int* rowof = reinterpret_cast<int*>(tr + nrow * TS);
+  const int item = xcd_item(n0 * ngroup * nbtot);
+  if (item < 0) return;
+  const int i0 = item / (ngroup * nbtot);
+  const int rem = item - i0 * ngroup * nbtot;
+  const int grp = rem / nbtot, b = rem - grp * nbtot;
+  const int per = (npt + ngroup - 1) / ngroup;
+  const int j0 = grp * per, j1 = min(npt, j0 + per);
+  fill_rowof<SN>(rowof, rows, nrow);
+  __syncthreads();
+  const int qd = threadIdx.x >> 2, e = threadIdx.x & 3;
+  const int64_t nr = (int64_t)n0 * PL;
+  // this lane's points: i1 = e M + m, i2 = qd
+  const int64_t pofs = (int64_t)i0 * PL + (int64_t)(e * M) * SN + qd;
+  T acc[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) acc[m] = T(0);
+  for (int j = j0; j < j1; ++j) {
+    cplx<T> x[M];
+    quad_plane_inverse<SN>(wst + ((int64_t)(b * npt + j) * n0 + i0) * nws, nrow, rows, rowof, tr,
+                           x);
+    if (qd < SN) {
+      const int v1 = 2 * j, v2 = 2 * j + 1;
+      const bool has2 = v2 < per_trial;
+      T* o1 = out + ((int64_t)b * per_trial + v1) * nr + pofs;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const T a = x[m].x * scale, c = x[m].y * scale;
+        o1[m * SN] = a;
+        if (has2) o1[nr + m * SN] = c;
+        if (drho) {
+          T d = phi[(int64_t)v1 * nr + pofs + m * SN] * a;
+          if (has2) d += phi[(int64_t)v2 * nr + pofs + m * SN] * c;
+          acc[m] += d;
+        }
+      }
+    }
+    __syncthreads();  // the next pack's rows overwrite the transpose buffer
+  }
+  if (drho && qd < SN) {
+    T* d = drho + ((int64_t)grp * nbtot + b) * nr + pofs;
+#pragma unroll
+    for (int m = 0; m < M; ++m) d[m * SN] = acc[m];
+  }
+}
+
+// real fields -> wave sticks: columns (along i1) from the two fields of a
+// pack, the wave-stick rows through LDS, then the rows (along i2)
+template <int SN, typename T>
+__global__ void __launch_bounds__(quad_threads(SN))
+k_fields_to_wsticks_q(const T* __restrict__ fields, int npt, int per_trial, int n0, int nws,
+                      int nrow, const int4* __restrict__ rows, cplx<T>* __restrict__ wst,
+                      int npack) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int M = SN / 4, TS = SN + 1, PL = SN * SN;
+  cplx<T>* tr = reinterpret_cast<cplx<T>*>(smem_raw);
+  int* rowof = reinterpret_cast<int*>(tr + nrow * TS);
+  const int item = xcd_item(n0 * npack);
+  if (item < 0) return;
+  const int i0 = item / npack;
+  const int pack = item - i0 * npack;
+  fill_rowof<SN>(rowof, rows, nrow);
+  __syncthreads();
+  const int qd = threadIdx.x >> 2, e = threadIdx.x & 3, qb = quad_block(e);
+  const int64_t nr = (int64_t)n0 * PL;
+  if (qd < SN) {
+    const int b = pack / npt, j = pack - b * npt;
+    const int v1 = 2 * j, v2 = 2 * j + 1;
+    const bool has2 = v2 < per_trial;
+    const T* f1 = fields + ((int64_t)b * per_trial + v1) * nr + (int64_t)i0 * PL +
+                  (int64_t)(e * M) * SN + qd;
+    const T* f2 = has2 ? f1 + nr : f1;
+    cplx<T> x[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const T a = f1[m * SN], c = f2[m * SN];
+      x[m] = {a, has2 ? c : T(0)};
+    }
+    fft_quad_fwd_contig<SN>(x, e);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int r = rowof[4 * k + qb];
+      if (r >= 0) tr[r * TS + qd] = x[k];
+    }
+  }
+  __syncthreads();
+  if (qd < nrow) {
+    cplx<T> x[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] = tr[qd * TS + e * M + m];
+    fft_quad_fwd_contig<SN>(x, e);
+    const int4 rw = rows[qd];
+    cplx<T>* o = wst + ((int64_t)pack * n0 + i0) * nws + rw.y;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const int p = row_pos(4 * k + qb, rw.z, SN);
+      if (p >= 0) o[p] = x[k];
     }
   }
 }
@@ -1078,6 +1340,39 @@ int plane_static_wave(const Geometry& g) {
   return (sn > 0 && g.nw <= ws * kPlaneThreads) ? sn : 0;
 }
 
+// the register-quad plane kernels: square planes of 24, 48, 72, 96 or 108
+// points whose stick sets are row-regular, taken where the complex plane and
+// its twiddles do not fit in LDS (FP64 108 x 108) or, with force, everywhere
+int quad_plane_size(const Geometry& g, size_t elem, bool force) {
+  const int n = g.n1 == g.n2 ? g.n1 : 0;
+  if (!(n == 24 || n == 48 || n == 72 || n == 96 || n == 108) || g.ndrow <= 0 || g.nwrow <= 0)
+    return 0;
+  const bool fits = (size_t)(n * n + n) * 2 * elem <= 160 * 1024;
+  return (force || !fits) ? n : 0;
+}
+
+#define WTD_QUAD_LAUNCH(K, T, nrow, items, stream, ...)                                      \
+  do {                                                                                       \
+    switch (g.quad_sn) {                                                                     \
+      WTD_QUAD_CASE(24, K, T, nrow, items, stream, __VA_ARGS__)                              \
+      WTD_QUAD_CASE(48, K, T, nrow, items, stream, __VA_ARGS__)                              \
+      WTD_QUAD_CASE(72, K, T, nrow, items, stream, __VA_ARGS__)                              \
+      WTD_QUAD_CASE(96, K, T, nrow, items, stream, __VA_ARGS__)                              \
+      WTD_QUAD_CASE(108, K, T, nrow, items, stream, __VA_ARGS__)                             \
+      default:                                                                               \
+        throw StatusError{WTD_ERR_SHAPE, "no register-quad plane kernel for this grid"};    \
+    }                                                                                        \
+    WTD_HIP(hipGetLastError());                                                              \
+  } while (0)
+#define WTD_QUAD_CASE(N, K, T, nrow, items, stream, ...)                                     \
+  case N: {                                                                                  \
+    const size_t l_ = (size_t)(nrow) * (N + 1) * sizeof(cplx<T>) + N * sizeof(int);          \
+    check_lds(l_);                                                                           \
+    set_lds((K<N, T>), l_);                                                                  \
+    hipLaunchKernelGGL((K<N, T>), dim3((unsigned)(((items) + 7) / 8 * 8)),                   \
+                       dim3(quad_threads(N)), l_, stream, __VA_ARGS__);                      \
+  } break;
+
 template <typename T>
 void launch_sphere_to_wsticks(const Geometry& g, const T* coef, int nfield, int npw, int nb,
                               int per_trial, cplx<T>* wst, hipStream_t s) {
@@ -1097,6 +1392,11 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   const int npt = (per_trial + 1) / 2;
   if (!drho || !part) ngroup = 1;
   ngroup = std::max(1, std::min(ngroup, npt));
+  if (g.quad_sn > 0) {
+    T* dt = (ngroup > 1) ? part : drho;
+    WTD_QUAD_LAUNCH(k_wsticks_to_fields_q, T, g.nwrow, g.n0 * nb * ngroup, s, wst, npt,
+                    per_trial, g.n0, g.nws, g.nwrow, g.wrows, scale, out, phi, dt, ngroup, nb);
+  } else {
   dim3 grid((unsigned)((g.n0 * nb * ngroup + 7) / 8 * 8));
   const int sn = plane_static_wave(g);
   // compile-time plans accumulate the density in registers, runtime plans in LDS
@@ -1106,6 +1406,7 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
                       per_trial, g.n0, g.n1, g.n2,
                    g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), scale, out, phi, dtarget, ngroup, nb);
+  }
   if (ngroup > 1) {
     const int64_t n = (int64_t)nb * g.nr;
     hipLaunchKernelGGL(k_sum_groups<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
@@ -1117,6 +1418,11 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
 template <typename T>
 void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads, int npack,
                              int limit, cplx<T>* dst, hipStream_t s) {
+  if (g.quad_sn > 0) {
+    WTD_QUAD_LAUNCH(k_pairs_to_dsticks_q, T, g.ndrow, g.n0 * npack, s, src, quads, npack, limit,
+                    g.n0, g.nds, g.ndrow, g.drows, dst);
+    return;
+  }
   const int ps = plane_static(g);
   const int per_wg = (ps > 0 && ps * ps <= 72 * 72 && sizeof(T) == 8) ? kPairItems : 1;
   const int ngrp = (g.n0 * npack + per_wg - 1) / per_wg;
@@ -1144,6 +1450,11 @@ void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream
 template <typename T>
 void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, int nfield,
                               T* out, hipStream_t s, bool il) {
+  if (g.quad_sn > 0 && !il) {
+    WTD_QUAD_LAUNCH(k_dsticks_to_fields_q, T, g.ndrow, g.n0 * npack, s, dst, npack, nfield, g.n0,
+                    g.nds, g.ndrow, g.drows, out);
+    return;
+  }
   dim3 grid((unsigned)((g.n0 * npack + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_dsticks_to_fields, T, grid, lds, s, dst, npack, il ? 1 : 0, nfield, g.n0,
@@ -1176,6 +1487,11 @@ void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int pe
   (void)nfield_per_trial;
   const int npt = (per_trial + 1) / 2;
   const int npack = nb * npt;
+  if (g.quad_sn > 0) {
+    WTD_QUAD_LAUNCH(k_fields_to_wsticks_q, T, g.nwrow, g.n0 * npack, s, fields, npt, per_trial,
+                    g.n0, g.nws, g.nwrow, g.wrows, wst, npack);
+    return;
+  }
   const int items = plane_static(g) > 0 ? kPairItems : 1;
   const int ngrp = (g.n0 * npack + items - 1) / items;
   dim3 grid((unsigned)((ngrp + 7) / 8 * 8));

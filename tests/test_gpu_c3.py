@@ -7,8 +7,8 @@ gen.trials_random, the rows v = 0, 215, 431 of the D, K1d and K1e terms
 separately (written by tests/golden/make_golden.py c3rows, which calls only the
 oracle and the generator; the exchange sum runs over every v').  Each term is
 checked on its own (the D term dominates the sum, so a K-term mistake could
-hide under it), then the spin-conserving operator (c_K = 2) and the spin-flip
-one (c_K = 0, exchange only)."""
+hide under it), in FP32 and in FP64, then the spin-conserving operator
+(c_K = 2) and the spin-flip one (c_K = 0, exchange only)."""
 import os
 
 import numpy as np
@@ -65,12 +65,14 @@ def test_c3_spin_flip_rows_fp32(c3_case):
     assert err <= 2e-5
 
 
-def test_c3_fp64_plane_does_not_fit_lds(systems):
-    """A 108 x 108 FP64 plane (187 KB) exceeds the 160 KB of LDS of one
-    workgroup: context creation reports WTD_ERR_SHAPE instead of launching."""
-    from paper_2309_03513_amd import Liouville, WtdError
-    s = systems("c3")
-    say("c3 fp64 context creation (expected shape error)")
-    with pytest.raises(WtdError) as e:
-        Liouville(s, max_nb=1, precision="fp64")
-    assert e.value.status == -2
+@pytest.mark.parametrize("term", ["k1d", "k1e", "d"])
+def test_c3_term_rows_fp64(c3_case, term):
+    """FP64 at 108^3: the 108 x 108 FP64 plane (187 KB) does not fit in LDS, so
+    the plane transforms run on the register-quad kernels (lines in registers,
+    one LDS transpose per 2D FFT)."""
+    s, a, rows, ref = c3_case
+    mask = {"d": oracle.TERM_D, "k1d": oracle.TERM_K1D, "k1e": oracle.TERM_K1E}[term]
+    say(f"c3 {term} rows {rows} fp64")
+    err = rel_err(_apply(s, a, rows, "fp64", mask), ref[term])
+    say(f"  rel err {err:.3e}")
+    assert err <= 1e-10
