@@ -34,43 +34,49 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 876.1e6,
+        "bytes": 876.7e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "bb3a0e5730a38a1da72b21d5bd40476d0a31e7a7ae75b9789d8fc7f72e1ebd2d",
+                "a7003785add808e91a1d17ad03add473366802e8d267687db944d89ae4f4535f",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+            "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
+                "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1295.4e6,
+        "bytes": 1295.0e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "bb3a0e5730a38a1da72b21d5bd40476d0a31e7a7ae75b9789d8fc7f72e1ebd2d",
+                "a7003785add808e91a1d17ad03add473366802e8d267687db944d89ae4f4535f",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+            "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
+                "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
         },
     },
     "pair_plane_inv": {
         "bytes": 1983.3e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "bb3a0e5730a38a1da72b21d5bd40476d0a31e7a7ae75b9789d8fc7f72e1ebd2d",
+                "a7003785add808e91a1d17ad03add473366802e8d267687db944d89ae4f4535f",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+            "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
+                "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
         },
     },
     "contract": {
-        "bytes": 19675.0e6,
+        "bytes": 19723.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "d26b0dd0c5477ae388c97316741d0e3ffcfad827fb03bae3a8ba6a1cf8e374b7",
+                "845471063d7740dbee2ad66337f66b6d18ca4630b57c029aa96fcd35fc041773",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
         },

@@ -565,6 +565,10 @@ __device__ __forceinline__ void rr_put(float* s_t, const float (&v)[8][RRTile::P
     }
 }
 
+// rounds of tau loads in flight (deeper prefetch measured slower: 4 rounds
+// 6.30 ms, 5 rounds 6.65 ms against 6.03 ms per apply at 72^3)
+constexpr int kRRDepth = 3;
+
 __global__ void __launch_bounds__(RRTile::THREADS)
 k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ phi,
               const float* __restrict__ at, const float* __restrict__ tau,
@@ -625,9 +629,9 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
         L.dcol[it] = max(vl, wl);
       }
     }
-    // tau tiles of three rounds in flight (the memory latency under load spans
-    // several rounds of MFMA work)
-    float vb[3][8][C::PER];
+    // tau tiles of kRRDepth rounds in flight (the memory latency under load
+    // spans several rounds of MFMA work)
+    float vb[kRRDepth][8][C::PER];
     {
       float ta[8][C::PER];
 #pragma unroll
@@ -642,7 +646,7 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
         }
       __syncthreads();  // s_rowb
 #pragma unroll
-      for (int r = 0; r < 3; ++r) rr_fetch(vb[r], tau, s_rowb, L, r);
+      for (int r = 0; r < kRRDepth; ++r) rr_fetch(vb[r], tau, s_rowb, L, r);
 #pragma unroll
       for (int K = 0; K < 8; ++K)
 #pragma unroll
@@ -661,9 +665,9 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       __syncthreads();
-      rr_put(s_t, vb[r % 3], r);
+      rr_put(s_t, vb[r % kRRDepth], r);
       __syncthreads();
-      if (r + 3 < 8) rr_fetch(vb[r % 3], tau, s_rowb, L, r + 3);
+      if (r + kRRDepth < 8) rr_fetch(vb[r % kRRDepth], tau, s_rowb, L, r + kRRDepth);
       if (r == 5) load_response();
       int partner, slot;
       if (r < 7) {
