@@ -90,6 +90,9 @@ struct wtd_ctx {
   // layout the kept pair potentials were written in (4-pair interleaved or
   // [pair][N_r]); a later apply that reads the other layout forms them again
   bool tau_il = false;
+  // all pairs kept in the tile order of the round-robin contraction
+  // (rr_tile_base) rather than row-major
+  bool tile_pairs = false;
   void* wst = nullptr;       // [max packs][n0][nw] complex
   void* dst = nullptr;       // [pair chunk][n0][nd] complex
   void* ag = nullptr;        // [max_nb][nocc][2 npw]
@@ -560,6 +563,7 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
                 "WTD_ROW_BLOCK must be 0, 16, 32, 48 or 64");
     if (rb > 0) c->row_block = rb;
   }
+  c->tile_pairs = c->row_block == 0 && contract_rr_applies<T>(c->g, mnb, nocc);
   {
     std::vector<int2> pr;
     std::vector<int> pidx;
@@ -571,13 +575,26 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
         q.push_back(int4{a.x, a.y, b.x, b.y});
       }
     };
-    if (c->row_block == 0) {
+    auto add_pair = [&](int v, int w) {
+      pidx[(size_t)v * nocc + w] = pidx[(size_t)w * nocc + v] = (int)pr.size();
+      pr.push_back(int2{v, w});
+    };
+    if (c->tile_pairs) {
+      // 16 x 16 row tiles (I <= J) in the order the round-robin contraction
+      // addresses them: diagonal tiles as upper triangles, row by row
+      pidx.resize((size_t)nocc * nocc);
+      for (int I = 0; I < nocc / 16; ++I)
+        for (int J = I; J < nocc / 16; ++J) {
+          WTD_REQUIRE((int)pr.size() == rr_tile_base(I, J), WTD_ERR_SHAPE,
+                      "pair tile order");
+          for (int a = 0; a < 16; ++a)
+            for (int b = (I == J) ? a : 0; b < 16; ++b) add_pair(16 * I + a, 16 * J + b);
+        }
+      pack(0);
+    } else if (c->row_block == 0) {
       pidx.resize((size_t)nocc * nocc);
       for (int v = 0; v < nocc; ++v)
-        for (int w = v; w < nocc; ++w) {
-          pidx[(size_t)v * nocc + w] = pidx[(size_t)w * nocc + v] = (int)pr.size();
-          pr.push_back(int2{v, w});
-        }
+        for (int w = v; w < nocc; ++w) add_pair(v, w);
       pack(0);
     } else {
       // block pairs (A, B), A <= B; the diagonal block stores its upper
@@ -768,7 +785,7 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   // 5. pair potentials, in chunks of packed pairs; stored interleaved by groups
   // of kTauIl pairs when the round-robin contraction reads them (a chunk starts
   // on a whole group, so its groups start at field 2 p0 in either layout)
-  const bool il = contract_rr_applies<T>(g, nb, nocc);
+  const bool il = c->tile_pairs;
   if (k1d && !c->row_block && !(c->tau_cache && c->tau_valid && c->tau_il == il)) {
     WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
                 WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");

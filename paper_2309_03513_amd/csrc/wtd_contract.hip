@@ -457,7 +457,7 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// Round-robin form for Nocc = 128 (eight row tiles), FP32, full tiles.
+// Round-robin form for Nocc = 128 (eight row tiles of 16), FP32.
 //
 // Wave w owns row tile w: its accumulators hold R[w] (16 rows x 16 trials) for
 // all TP = 8 points of the workgroup, indexed at compile time, so the MFMA
@@ -467,23 +467,36 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
 // k = 1..3 (four off-diagonal tiles, each used by both of its waves, once
 // directly and once transposed); round 7 holds the eight diagonal tiles.
 // All eight trial tiles stay in LDS for the whole walk; the tau tiles of the
-// next round are fetched into registers while the current round computes.
+// next rounds are in flight in registers while the current round computes.
 //
-// LDS tile layout: element (q, p) at p * 264 + perm(q), perm(q) =
-// q ^ (((q >> 6) & 3) << 2).  The point stride (264 = 8 mod 64 words) and the
-// permutation make the MFMA operand reads (fixed point, lanes over (lx, ly))
-// and the staging stores (lanes over 8 points x 8 pairs) each touch 64
-// distinct banks, and the eight points of one q are reached through
-// immediate offsets.
+// tau holds the pairs tile by tile (rr_tile_base) in the 4-pair interleaved
+// layout, so a 16-byte load reads four pairs of one tile row at one point and
+// the eight lanes of one group read one whole 128-byte line.  An off-diagonal
+// tile is one such load per thread; a diagonal round (eight packed triangles
+// of 34 groups) at most five.  Few, wide loads keep several rounds in flight
+// within the per-wave limit on outstanding loads.
+//
+// LDS tile layout: element (q, p) of a square tile, q = 16 row + column, at
+// p * 264 + perm(q), perm(q) = q ^ (((q >> 6) & 3) << 2): the point stride and
+// the permutation spread the MFMA operand reads (fixed point, lanes over
+// (lx, ly)) over the banks, and the permutation keeps aligned runs of four q
+// together, so a staged load is one 16-byte store.  A diagonal tile is kept as
+// its packed triangle: element (k, p) at p * 264 + k.
 struct RRTile {
-  static constexpr int TP = 8;
+  static constexpr int TP = 8;              // points per workgroup
   static constexpr int THREADS = 512;
   static constexpr int PS = 264;            // point stride (words)
   static constexpr int NE = PS * TP;        // words per tile
-  static constexpr int PER = 256 * TP / THREADS;  // tile elements staged per thread
+  static constexpr int DIAG = 8 * 34 * TP;  // 16-byte loads of a diagonal round
+  static constexpr int DIAG_LOADS = (DIAG + THREADS - 1) / THREADS;
   static __device__ __forceinline__ int perm(int q) { return q ^ (((q >> 6) & 3) << 2); }
   static __device__ __forceinline__ int at(int q, int p) { return p * PS + perm(q); }
 };
+static_assert(kTauIl == 4, "the round-robin staging loads one 4-pair group per 16 bytes");
+static_assert(rr_tile_base(7, 7) + 136 == 128 * 129 / 2, "the tile order covers the pair triangle");
+static_assert(256 * RRTile::TP / 4 == RRTile::THREADS, "one 16-byte load per thread per tile");
+
+typedef float rr_f4 __attribute__((ext_vector_type(4)));
 
 // partner of row tile w in round r (r < 7), and the slot of the pair's tile
 __device__ __forceinline__ void rr_pair(int r, int w, int& partner, int& slot) {
@@ -511,63 +524,9 @@ __device__ __forceinline__ void rr_tile(int r, int slot, int& I, int& J) {
   J = max(a, b);
 }
 
-// Per-thread constants of the tau staging: thread t stages point p = t % 8 and
-// combos c = g + 64 it (g = t / 8): row v_loc = (g >> 4) + 4 it, column w_loc = g & 15.
-// tau is in the kTauIl-interleaved layout: pair P at point r is element
-// ((P / kTauIl) N_r + r) kTauIl + P % kTauIl, so the 8 points of one staging
-// load read kTauIl consecutive pairs as one contiguous run.
-struct RRLoad {
-  int64_t nrs;        // kTauIl N_r
-  int64_t rps;        // kTauIl r of this thread's point
-  int wl;             // w_loc
-  int vrow[4];        // v_loc
-  int drow[4];        // min(v_loc, w_loc)
-  int dcol[4];        // max(v_loc, w_loc)
-};
-
-__device__ __forceinline__ float rr_elem(const float* __restrict__ tau, const RRLoad& L, int P) {
-  return tau[(int64_t)(P >> kTauIlShift) * L.nrs + L.rps + (P & (kTauIl - 1))];
-}
-
-// Issue the global loads of round r's tau tiles (4 tiles, or 8 on the diagonal);
-// rowb[v] is the pair index of (v, v) minus v
-__device__ __forceinline__ void rr_fetch(float (&v)[8][RRTile::PER], const float* __restrict__ tau,
-                                         const int* rowb, const RRLoad& L, int r) {
-  if (r < 7) {
-#pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      int I, J;
-      rr_tile(r, sl, I, J);
-#pragma unroll
-      for (int it = 0; it < RRTile::PER; ++it)
-        v[sl][it] = rr_elem(tau, L, rowb[I * 16 + L.vrow[it]] + J * 16 + L.wl);
-    }
-  } else {
-#pragma unroll
-    for (int sl = 0; sl < 8; ++sl) {
-#pragma unroll
-      for (int it = 0; it < RRTile::PER; ++it)
-        v[sl][it] = rr_elem(tau, L, rowb[sl * 16 + L.drow[it]] + sl * 16 + L.dcol[it]);
-    }
-  }
-}
-
-__device__ __forceinline__ void rr_put(float* s_t, const float (&v)[8][RRTile::PER], int r) {
-  const int p = threadIdx.x % RRTile::TP;
-  const int g = threadIdx.x / RRTile::TP;
-  const int ntl = (r == 7) ? 8 : 4;
-#pragma unroll
-  for (int sl = 0; sl < 8; ++sl)
-    if (sl < ntl) {
-#pragma unroll
-      for (int it = 0; it < RRTile::PER; ++it)
-        s_t[sl * RRTile::NE + RRTile::at(g + it * (RRTile::THREADS / RRTile::TP), p)] = v[sl][it];
-    }
-}
-
-// rounds of tau loads in flight (deeper prefetch measured slower: 4 rounds
-// 6.30 ms, 5 rounds 6.65 ms against 6.03 ms per apply at 72^3)
-constexpr int kRRDepth = 3;
+// rounds of tau loads in flight (with 16-byte loads, two rounds measured
+// fastest: 2, 3, 4 and 6 rounds at 72^3 took 4.32, 4.40, 4.54 and 4.96 ms)
+constexpr int kRRDepth = 2;
 
 __global__ void __launch_bounds__(RRTile::THREADS)
 k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ phi,
@@ -579,95 +538,124 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
   typedef Mfma<float>::acc_t acc_t;
   __shared__ float s_a[8 * C::NE];   // trial tiles a~[b0 + b][16 K + v'], K = 0..7
   __shared__ float s_t[8 * C::NE];   // tau tiles of one round; reused to stage R
-  __shared__ int s_rowb[128];        // pair (v, w >= v) has index s_rowb[v] + w
   const int per = (ntile + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntile) return;
   const int b0 = blockIdx.y * 16;
   const int64_t r0 = (int64_t)tile * C::TP;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
   const int lx = lane & 15, ly = lane >> 4;
-  const int p_ld = threadIdx.x % C::TP;
-  const int g_ld = threadIdx.x / C::TP;
-  const int64_t rp = r0 + p_ld;
-  for (int v = threadIdx.x; v < 128; v += blockDim.x) s_rowb[v] = v * nocc - v * (v + 1) / 2;
+  const rr_f4* __restrict__ tau4 = reinterpret_cast<const rr_f4*>(tau);
+
+  // off-diagonal tiles: thread t loads group g = t / 8 of the tile (row g / 4,
+  // columns 4 (g % 4) .. + 3) at point t % 8
+  const int tp = t & 7, tg = t >> 3;
+  const int64_t toff = (int64_t)tg * nr + r0 + tp;
+  const int tput = tp * C::PS + C::perm(4 * tg);
+  // diagonal round: load j of thread t is element t + 512 j of the eight
+  // triangles x 34 groups x 8 points
+  int64_t doff[C::DIAG_LOADS];
+  int dput[C::DIAG_LOADS];
+#pragma unroll
+  for (int j = 0; j < C::DIAG_LOADS; ++j) {
+    const int idx = min(t + C::THREADS * j, C::DIAG - 1);
+    const int dt = idx / (34 * C::TP), m = idx - dt * 34 * C::TP;
+    const int k4 = m / C::TP, p = m % C::TP;
+    doff[j] = (int64_t)(rr_tile_base(dt, dt) / kTauIl + k4) * nr + r0 + p;
+    dput[j] = dt * C::NE + p * C::PS + 4 * k4;
+  }
+  const bool dlast = t + C::THREADS * (C::DIAG_LOADS - 1) < C::DIAG;
+  auto fetch = [&](rr_f4 (&v)[C::DIAG_LOADS], int r) {
+    if (r < 7) {
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        int I, J;
+        rr_tile(r, sl, I, J);
+        v[sl] = tau4[(int64_t)(rr_tile_base(I, J) / kTauIl) * nr + toff];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < C::DIAG_LOADS; ++j)
+        if (j < C::DIAG_LOADS - 1 || dlast) v[j] = tau4[doff[j]];
+    }
+  };
+  auto put = [&](const rr_f4 (&v)[C::DIAG_LOADS], int r) {
+    if (r < 7) {
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) *reinterpret_cast<rr_f4*>(s_t + sl * C::NE + tput) = v[sl];
+    } else {
+#pragma unroll
+      for (int j = 0; j < C::DIAG_LOADS; ++j)
+        if (j < C::DIAG_LOADS - 1 || dlast) *reinterpret_cast<rr_f4*>(s_t + dput[j]) = v[j];
+    }
+  };
 
   acc_t acc[C::TP];
 #pragma unroll
   for (int p = 0; p < C::TP; ++p) acc[p] = acc_t{0, 0, 0, 0};
 
-  // response-term inputs of this thread's output elements, loaded during the
-  // last rounds: phi[16 K + v_loc][r], v_H[b][r], drho[b][r], f_xc[r]
-  float ph[8][C::PER] = {};
-  float vhb = 0.f, drb = 0.f, fx = 0.f;
+  // trial and output rows of thread t: trial b = b0 + (t / 2) % 16, orbital
+  // v_j = t / 32 + 16 j (j = 0..7), points 4 (t % 2) .. + 3
+  const int h = t & 1, bl = (t >> 1) & 15;
+  const bool bin = b0 + bl < nb;
+  const int64_t rq = r0 + 4 * h;
+  // response-term inputs of these outputs, loaded during the last rounds
+  rr_f4 ph[8], vhb = {0.f, 0.f, 0.f, 0.f}, drb = vhb, fx = vhb;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ph[j] = vhb;
   auto load_response = [&]() {
-    const int b = b0 + (g_ld & 15);
-    if (k1e && b < nb) {
+    if (k1e && bin) {
 #pragma unroll
-      for (int K = 0; K < 8; ++K)
-#pragma unroll
-        for (int it = 0; it < C::PER; ++it)
-          ph[K][it] = phi[(int64_t)(K * 16 + (g_ld >> 4) + 4 * it) * nr + rp];
-      vhb = vh[(int64_t)b * nr + rp];
-      drb = drho[(int64_t)b * nr + rp];
-      fx = fxc[rp];
+      for (int j = 0; j < 8; ++j)
+        ph[j] = *reinterpret_cast<const rr_f4*>(phi + (int64_t)((t >> 5) + 16 * j) * nr + rq);
+      vhb = *reinterpret_cast<const rr_f4*>(vh + (int64_t)(b0 + bl) * nr + rq);
+      drb = *reinterpret_cast<const rr_f4*>(drho + (int64_t)(b0 + bl) * nr + rq);
+      fx = *reinterpret_cast<const rr_f4*>(fxc + rq);
     }
   };
 
   if (k1d) {
-    RRLoad L;
+    rr_f4 vb[kRRDepth][C::DIAG_LOADS];
     {
-      const int wl = g_ld & 15;
-      L.nrs = nr * kTauIl;
-      L.rps = rp * kTauIl;
-      L.wl = wl;
+      rr_f4 ta[8];
 #pragma unroll
-      for (int it = 0; it < C::PER; ++it) {
-        const int vl = (g_ld >> 4) + 4 * it;
-        L.vrow[it] = vl;
-        L.drow[it] = min(vl, wl);
-        L.dcol[it] = max(vl, wl);
+      for (int j = 0; j < 8; ++j) {
+        // trials past nb (a ragged last trial tile) enter as zeros
+        const int v = (t >> 5) + 16 * j;
+        ta[j] = bin ? *reinterpret_cast<const rr_f4*>(at + ((int64_t)(b0 + bl) * nocc + v) * nr + rq)
+                    : rr_f4{0.f, 0.f, 0.f, 0.f};
       }
-    }
-    // tau tiles of kRRDepth rounds in flight (the memory latency under load
-    // spans several rounds of MFMA work)
-    float vb[kRRDepth][8][C::PER];
-    {
-      float ta[8][C::PER];
 #pragma unroll
-      for (int K = 0; K < 8; ++K)
+      for (int r = 0; r < kRRDepth; ++r) fetch(vb[r], r);
 #pragma unroll
-        for (int it = 0; it < C::PER; ++it) {
-          const int c = g_ld + it * (C::THREADS / C::TP);
-          // trials past nb (a ragged last trial tile) enter as zeros
-          ta[K][it] = (b0 + (c & 15) < nb)
-                          ? at[((int64_t)(b0 + (c & 15)) * nocc + K * 16 + (c >> 4)) * nr + rp]
-                          : 0.f;
-        }
-      __syncthreads();  // s_rowb
-#pragma unroll
-      for (int r = 0; r < kRRDepth; ++r) rr_fetch(vb[r], tau, s_rowb, L, r);
-#pragma unroll
-      for (int K = 0; K < 8; ++K)
-#pragma unroll
-        for (int it = 0; it < C::PER; ++it)
-          s_a[K * C::NE + C::at(g_ld + it * (C::THREADS / C::TP), p_ld)] = ta[K][it];
+      for (int j = 0; j < 8; ++j) {
+        const int v = (t >> 5) + 16 * j;
+        float* d = s_a + (v >> 4) * C::NE + C::at((v & 15) * 16 + bl, 4 * h);
+        d[0] = ta[j].x;
+        d[C::PS] = ta[j].y;
+        d[2 * C::PS] = ta[j].z;
+        d[3 * C::PS] = ta[j].w;
+      }
     }
     // lane-constant LDS offsets of the MFMA operands for K-step s4:
     // direct A[m = lx][k = 4 s4 + ly] = tau[v = lx][w = 4 s4 + ly];
-    // transposed A = tau[v = 4 s4 + ly][w = lx]; B[k = v'][n = b] = a~[4 s4 + ly][lx]
-    int oa_d[4], oa_t[4];
+    // transposed A = tau[v = 4 s4 + ly][w = lx]; diagonal A = the triangle
+    // element of (min, max); B[k = v'][n = b] = a~[4 s4 + ly][lx]
+    int oa_d[4], oa_t[4], oa_r[4];
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
-      oa_d[s4] = C::perm(lx * 16 + 4 * s4 + ly);
-      oa_t[s4] = C::perm((4 * s4 + ly) * 16 + lx);
+      const int k = 4 * s4 + ly;
+      oa_d[s4] = C::perm(lx * 16 + k);
+      oa_t[s4] = C::perm(k * 16 + lx);
+      oa_r[s4] = rr_tri_index(min(lx, k), max(lx, k));
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       __syncthreads();
-      rr_put(s_t, vb[r % kRRDepth], r);
+      put(vb[r % kRRDepth], r);
       __syncthreads();
-      if (r + kRRDepth < 8) rr_fetch(vb[r % kRRDepth], tau, s_rowb, L, r + kRRDepth);
+      if (r + kRRDepth < 8) fetch(vb[r % kRRDepth], r + kRRDepth);
       if (r == 5) load_response();
       int partner, slot;
       if (r < 7) {
@@ -684,7 +672,7 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
 #pragma unroll
       for (int s4 = 0; s4 < 5; ++s4) {
         if (s4 < 4) {
-          const float* pa = st + (direct ? oa_d[s4] : oa_t[s4]);
+          const float* pa = st + (r == 7 ? oa_r[s4] : direct ? oa_d[s4] : oa_t[s4]);
           const float* pb = sa + oa_t[s4];
 #pragma unroll
           for (int p = 0; p < C::TP; ++p) {
@@ -711,17 +699,17 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
 #pragma unroll
     for (int e = 0; e < 4; ++e) so[C::at(Mfma<float>::row(lane, e) * 16 + lx, p)] = acc[p][e];
   __syncthreads();
-  const float vb_resp = vhb + fx * drb;
+  if (!bin) return;
+  const rr_f4 vb_resp = vhb + fx * drb;
 #pragma unroll
-  for (int K = 0; K < 8; ++K)
-#pragma unroll
-    for (int it = 0; it < C::PER; ++it) {
-      const int c = g_ld + it * (C::THREADS / C::TP);
-      const int v = K * 16 + (c >> 4), b = b0 + (c & 15);
-      float val = -alpha * s_t[K * C::NE + C::at(c, p_ld)];
-      if (k1e) val += ck * ph[K][it] * vb_resp;
-      if (b < nb) R[((int64_t)b * nocc + v) * nr + rp] = val;
-    }
+  for (int j = 0; j < 8; ++j) {
+    const int v = (t >> 5) + 16 * j;
+    const float* src = s_t + (v >> 4) * C::NE + C::at((v & 15) * 16 + bl, 4 * h);
+    rr_f4 val = {-alpha * src[0], -alpha * src[C::PS], -alpha * src[2 * C::PS],
+                 -alpha * src[3 * C::PS]};
+    if (k1e) val += ck * ph[j] * vb_resp;
+    *reinterpret_cast<rr_f4*>(R + ((int64_t)(b0 + bl) * nocc + v) * nr + rq) = val;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -903,8 +891,10 @@ bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, con
                           bool k1e, bool k1d, T* R, hipStream_t s, bool tau_il) {
   const int nt = (nocc + 15) / 16;
   if (nt > 8) return false;
+  WTD_REQUIRE(!tau_il || contract_rr_applies<T>(g, nb, nocc), WTD_ERR_SHAPE,
+              "tile-ordered pair potentials need the round-robin contraction");
   if constexpr (sizeof(T) == 4) {
-    if (tau_il && contract_rr_applies<T>(g, nb, nocc)) {
+    if (tau_il) {
       const int64_t nt64 = g.nr / RRTile::TP;
       WTD_REQUIRE(nt64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
       const int ntile = (int)nt64;

@@ -120,10 +120,24 @@ void launch_contract(const Geometry& g, int nb, int nocc, const T* phi, const T*
                      const T* tau, const int* pair_index, const T* vh, const T* drho,
                      const T* fxc, T ck, T alpha, bool k1e, bool k1d, T* R, hipStream_t s);
 
+// Pair order of the round-robin contraction (FP32, Nocc = 128, all pairs at
+// once): the 36 tiles (I <= J) of 16 x 16 occupied rows in row-major tile
+// order; a diagonal tile holds its upper triangle row by row (136 pairs, the
+// pair (16 I + a, 16 I + b), a <= b, at rr_tri_index(a, b)), an off-diagonal
+// tile its full square row-major (256 pairs).  Both counts are multiples of
+// kTauIl, so every tile starts on a whole interleave group.
+__host__ __device__ constexpr int rr_tile_base(int I, int J) {
+  return 136 * I + 256 * (7 * I - I * (I - 1) / 2) + (J > I ? 136 + 256 * (J - I - 1) : 0);
+}
+__host__ __device__ constexpr int rr_tri_index(int a, int b) {
+  return 16 * a - a * (a - 1) / 2 + (b - a);
+}
+
 // MFMA contraction for Nocc <= 128 (wtd_contract.hip); returns false if not applicable.
-// tau is [pair][N_r] (pairs v <= v' row-major), or, when tau_il is set and
-// contract_rr_applies() (FP32, Nocc = 128, any nb), the same pairs in the
-// kTauIl-interleaved layout read by the round-robin kernel.
+// tau is [pair][N_r] (pairs v <= v' row-major); with tau_il set (only where
+// contract_rr_applies(): FP32, Nocc = 128, N_r a multiple of 8, any nb) it
+// holds the pairs in the tile order above, in the kTauIl-interleaved layout
+// read by the round-robin kernel.
 template <typename T>
 bool contract_rr_applies(const Geometry& g, int nb, int nocc);
 template <typename T>
