@@ -457,24 +457,24 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// Round-robin form for Nocc = 128 (eight row tiles of 16), FP32.
+// Round-robin form for Nocc = 128 (eight row tiles of 16), FP32 and FP64.
 //
 // Wave w owns row tile w: its accumulators hold R[w] (16 rows x 16 trials) for
-// all TP = 8 points of the workgroup, indexed at compile time, so the MFMA
-// chains of the eight points are independent.  The 36 tau tiles of the upper
-// triangle are visited in 8 rounds of a round-robin tournament: in round
-// r < 7 the row tiles pair up as {r, 7} and {(r + k) mod 7, (r - k) mod 7},
+// all TP points of the workgroup (8 in FP32, 4 in FP64), indexed at compile
+// time, so the MFMA chains of the points are independent.  The 36 tau tiles of
+// the upper triangle are visited in 8 rounds of a round-robin tournament: in
+// round r < 7 the row tiles pair up as {r, 7} and {(r + k) mod 7, (r - k) mod 7},
 // k = 1..3 (four off-diagonal tiles, each used by both of its waves, once
 // directly and once transposed); round 7 holds the eight diagonal tiles.
 // All eight trial tiles stay in LDS for the whole walk; the tau tiles of the
 // next rounds are in flight in registers while the current round computes.
 //
 // tau holds the pairs tile by tile (rr_tile_base) in the 4-pair interleaved
-// layout, so a 16-byte load reads four pairs of one tile row at one point and
-// the eight lanes of one group read one whole 128-byte line.  An off-diagonal
-// tile is one such load per thread; a diagonal round (eight packed triangles
-// of 34 groups) at most five.  Few, wide loads keep several rounds in flight
-// within the per-wave limit on outstanding loads.
+// layout, so the 16-byte loads of one group at the TP points of a workgroup
+// read one whole 128-byte line.  An off-diagonal tile is one 16-byte load per
+// thread; a diagonal round (eight packed triangles of 34 groups) at most five.
+// Few, wide loads keep several rounds in flight within the per-wave limit on
+// outstanding loads.
 //
 // LDS tile layout: element (q, p) of a square tile, q = 16 row + column, at
 // p * 264 + perm(q), perm(q) = q ^ (((q >> 6) & 3) << 2): the point stride and
@@ -482,21 +482,27 @@ k_contract_mfma(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ p
 // (lx, ly)) over the banks, and the permutation keeps aligned runs of four q
 // together, so a staged load is one 16-byte store.  A diagonal tile is kept as
 // its packed triangle: element (k, p) at p * 264 + k.
+template <typename T>
 struct RRTile {
-  static constexpr int TP = 8;              // points per workgroup
+  static constexpr int TP = 32 / sizeof(T);       // points per workgroup
   static constexpr int THREADS = 512;
-  static constexpr int PS = 264;            // point stride (words)
-  static constexpr int NE = PS * TP;        // words per tile
-  static constexpr int DIAG = 8 * 34 * TP;  // 16-byte loads of a diagonal round
+  static constexpr int PS = 264;                  // point stride (elements)
+  static constexpr int NE = PS * TP;              // elements per tile
+  static constexpr int EPL = 16 / sizeof(T);      // elements per 16-byte load
+  static constexpr int LPG = 4 / EPL;             // loads per 4-pair group and point
+  static constexpr int DIAG = 8 * 34 * TP * LPG;  // 16-byte loads of a diagonal round
   static constexpr int DIAG_LOADS = (DIAG + THREADS - 1) / THREADS;
   static __device__ __forceinline__ int perm(int q) { return q ^ (((q >> 6) & 3) << 2); }
   static __device__ __forceinline__ int at(int q, int p) { return p * PS + perm(q); }
 };
-static_assert(kTauIl == 4, "the round-robin staging loads one 4-pair group per 16 bytes");
+static_assert(kTauIl == 4, "the round-robin staging reads 4-pair groups");
 static_assert(rr_tile_base(7, 7) + 136 == 128 * 129 / 2, "the tile order covers the pair triangle");
-static_assert(256 * RRTile::TP / 4 == RRTile::THREADS, "one 16-byte load per thread per tile");
+static_assert(64 * RRTile<float>::TP * RRTile<float>::LPG == RRTile<float>::THREADS &&
+                  64 * RRTile<double>::TP * RRTile<double>::LPG == RRTile<double>::THREADS,
+              "one 16-byte load per thread per tile");
 
-typedef float rr_f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+using rr_vec = T __attribute__((ext_vector_type(16 / sizeof(T))));
 
 // partner of row tile w in round r (r < 7), and the slot of the pair's tile
 __device__ __forceinline__ void rr_pair(int r, int w, int& partner, int& slot) {
@@ -524,118 +530,122 @@ __device__ __forceinline__ void rr_tile(int r, int slot, int& I, int& J) {
   J = max(a, b);
 }
 
-// rounds of tau loads in flight (with 16-byte loads, two rounds measured
-// fastest: 2, 3, 4 and 6 rounds at 72^3 took 4.32, 4.40, 4.54 and 4.96 ms)
+// rounds of tau loads in flight (FP32 with 16-byte loads: 2, 3, 4 and 6 rounds
+// at 72^3 took 4.32, 4.40, 4.54 and 4.96 ms)
 constexpr int kRRDepth = 2;
 
-__global__ void __launch_bounds__(RRTile::THREADS)
-k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ phi,
-              const float* __restrict__ at, const float* __restrict__ tau,
-              const float* __restrict__ vh, const float* __restrict__ drho,
-              const float* __restrict__ fxc, float ck, float alpha, int k1e, int k1d,
-              float* __restrict__ R) {
-  typedef RRTile C;
-  typedef Mfma<float>::acc_t acc_t;
-  __shared__ float s_a[8 * C::NE];   // trial tiles a~[b0 + b][16 K + v'], K = 0..7
-  __shared__ float s_t[8 * C::NE];   // tau tiles of one round; reused to stage R
+template <typename T>
+__global__ void __launch_bounds__(RRTile<T>::THREADS)
+k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const T* __restrict__ phi,
+              const T* __restrict__ at, const T* __restrict__ tau, const T* __restrict__ vh,
+              const T* __restrict__ drho, const T* __restrict__ fxc, T ck, T alpha, int k1e,
+              int k1d, T* __restrict__ R) {
+  typedef RRTile<T> C;
+  typedef rr_vec<T> V;
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int TP = C::TP, EPL = C::EPL, LPG = C::LPG;
+  __shared__ T s_a[8 * C::NE];   // trial tiles a~[b0 + b][16 K + v'], K = 0..7
+  __shared__ T s_t[8 * C::NE];   // tau tiles of one round; reused to stage R
   const int per = (ntile + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntile) return;
   const int b0 = blockIdx.y * 16;
-  const int64_t r0 = (int64_t)tile * C::TP;
+  const int64_t r0 = (int64_t)tile * TP;
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int lx = lane & 15, ly = lane >> 4;
-  const rr_f4* __restrict__ tau4 = reinterpret_cast<const rr_f4*>(tau);
+  // tau as 16-byte vectors: the load `sub` of group G at point r is vector
+  // (G N_r + r) LPG + sub
+  const V* __restrict__ tauv = reinterpret_cast<const V*>(tau);
 
-  // off-diagonal tiles: thread t loads group g = t / 8 of the tile (row g / 4,
-  // columns 4 (g % 4) .. + 3) at point t % 8
-  const int tp = t & 7, tg = t >> 3;
-  const int64_t toff = (int64_t)tg * nr + r0 + tp;
-  const int tput = tp * C::PS + C::perm(4 * tg);
+  // off-diagonal tiles: thread t loads part sub = t % LPG of group
+  // g = t / (LPG TP) of the tile (row g / 4, columns 4 (g % 4) .. + 3) at
+  // point (t / LPG) % TP
+  const int tsub = t % LPG, tp = (t / LPG) % TP, tg = t / (LPG * TP);
+  const int64_t toff = ((int64_t)tg * nr + r0 + tp) * LPG + tsub;
+  const int tput = tp * C::PS + C::perm(4 * tg) + EPL * tsub;
   // diagonal round: load j of thread t is element t + 512 j of the eight
-  // triangles x 34 groups x 8 points
+  // triangles x 34 groups x TP points x LPG parts
   int64_t doff[C::DIAG_LOADS];
   int dput[C::DIAG_LOADS];
 #pragma unroll
   for (int j = 0; j < C::DIAG_LOADS; ++j) {
     const int idx = min(t + C::THREADS * j, C::DIAG - 1);
-    const int dt = idx / (34 * C::TP), m = idx - dt * 34 * C::TP;
-    const int k4 = m / C::TP, p = m % C::TP;
-    doff[j] = (int64_t)(rr_tile_base(dt, dt) / kTauIl + k4) * nr + r0 + p;
-    dput[j] = dt * C::NE + p * C::PS + 4 * k4;
+    const int dt = idx / (34 * TP * LPG), m = idx - dt * 34 * TP * LPG;
+    const int sub = m % LPG, p = (m / LPG) % TP, k4 = m / (LPG * TP);
+    doff[j] = ((int64_t)(rr_tile_base(dt, dt) / kTauIl + k4) * nr + r0 + p) * LPG + sub;
+    dput[j] = dt * C::NE + p * C::PS + 4 * k4 + EPL * sub;
   }
   const bool dlast = t + C::THREADS * (C::DIAG_LOADS - 1) < C::DIAG;
-  auto fetch = [&](rr_f4 (&v)[C::DIAG_LOADS], int r) {
+  auto fetch = [&](V (&v)[C::DIAG_LOADS], int r) {
     if (r < 7) {
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         int I, J;
         rr_tile(r, sl, I, J);
-        v[sl] = tau4[(int64_t)(rr_tile_base(I, J) / kTauIl) * nr + toff];
+        v[sl] = tauv[(int64_t)(rr_tile_base(I, J) / kTauIl) * nr * LPG + toff];
       }
     } else {
 #pragma unroll
       for (int j = 0; j < C::DIAG_LOADS; ++j)
-        if (j < C::DIAG_LOADS - 1 || dlast) v[j] = tau4[doff[j]];
+        if (j < C::DIAG_LOADS - 1 || dlast) v[j] = tauv[doff[j]];
     }
   };
-  auto put = [&](const rr_f4 (&v)[C::DIAG_LOADS], int r) {
+  auto put = [&](const V (&v)[C::DIAG_LOADS], int r) {
     if (r < 7) {
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) *reinterpret_cast<rr_f4*>(s_t + sl * C::NE + tput) = v[sl];
+      for (int sl = 0; sl < 4; ++sl) *reinterpret_cast<V*>(s_t + sl * C::NE + tput) = v[sl];
     } else {
 #pragma unroll
       for (int j = 0; j < C::DIAG_LOADS; ++j)
-        if (j < C::DIAG_LOADS - 1 || dlast) *reinterpret_cast<rr_f4*>(s_t + dput[j]) = v[j];
+        if (j < C::DIAG_LOADS - 1 || dlast) *reinterpret_cast<V*>(s_t + dput[j]) = v[j];
     }
   };
 
-  acc_t acc[C::TP];
+  acc_t acc[TP];
 #pragma unroll
-  for (int p = 0; p < C::TP; ++p) acc[p] = acc_t{0, 0, 0, 0};
+  for (int p = 0; p < TP; ++p) acc[p] = acc_t{0, 0, 0, 0};
 
   // trial and output rows of thread t: trial b = b0 + (t / 2) % 16, orbital
-  // v_j = t / 32 + 16 j (j = 0..7), points 4 (t % 2) .. + 3
+  // v_j = t / 32 + 16 j (j = 0..7), points EPL (t % 2) .. + EPL - 1
   const int h = t & 1, bl = (t >> 1) & 15;
   const bool bin = b0 + bl < nb;
-  const int64_t rq = r0 + 4 * h;
+  const int64_t rq = r0 + EPL * h;
+  const V zero = V(T(0));
   // response-term inputs of these outputs, loaded during the last rounds
-  rr_f4 ph[8], vhb = {0.f, 0.f, 0.f, 0.f}, drb = vhb, fx = vhb;
+  V ph[8], vhb = zero, drb = zero, fx = zero;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) ph[j] = vhb;
+  for (int j = 0; j < 8; ++j) ph[j] = zero;
   auto load_response = [&]() {
     if (k1e && bin) {
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        ph[j] = *reinterpret_cast<const rr_f4*>(phi + (int64_t)((t >> 5) + 16 * j) * nr + rq);
-      vhb = *reinterpret_cast<const rr_f4*>(vh + (int64_t)(b0 + bl) * nr + rq);
-      drb = *reinterpret_cast<const rr_f4*>(drho + (int64_t)(b0 + bl) * nr + rq);
-      fx = *reinterpret_cast<const rr_f4*>(fxc + rq);
+        ph[j] = *reinterpret_cast<const V*>(phi + (int64_t)((t >> 5) + 16 * j) * nr + rq);
+      vhb = *reinterpret_cast<const V*>(vh + (int64_t)(b0 + bl) * nr + rq);
+      drb = *reinterpret_cast<const V*>(drho + (int64_t)(b0 + bl) * nr + rq);
+      fx = *reinterpret_cast<const V*>(fxc + rq);
     }
   };
 
   if (k1d) {
-    rr_f4 vb[kRRDepth][C::DIAG_LOADS];
+    V vb[kRRDepth][C::DIAG_LOADS];
     {
-      rr_f4 ta[8];
+      V ta[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         // trials past nb (a ragged last trial tile) enter as zeros
         const int v = (t >> 5) + 16 * j;
-        ta[j] = bin ? *reinterpret_cast<const rr_f4*>(at + ((int64_t)(b0 + bl) * nocc + v) * nr + rq)
-                    : rr_f4{0.f, 0.f, 0.f, 0.f};
+        ta[j] = bin ? *reinterpret_cast<const V*>(at + ((int64_t)(b0 + bl) * nocc + v) * nr + rq)
+                    : zero;
       }
 #pragma unroll
       for (int r = 0; r < kRRDepth; ++r) fetch(vb[r], r);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int v = (t >> 5) + 16 * j;
-        float* d = s_a + (v >> 4) * C::NE + C::at((v & 15) * 16 + bl, 4 * h);
-        d[0] = ta[j].x;
-        d[C::PS] = ta[j].y;
-        d[2 * C::PS] = ta[j].z;
-        d[3 * C::PS] = ta[j].w;
+        T* d = s_a + (v >> 4) * C::NE + C::at((v & 15) * 16 + bl, EPL * h);
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) d[e * C::PS] = ta[j][e];
       }
     }
     // lane-constant LDS offsets of the MFMA operands for K-step s4:
@@ -664,26 +674,26 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
         partner = w;
         slot = w;
       }
-      const float* st = s_t + slot * C::NE;
-      const float* sa = s_a + partner * C::NE;
+      const T* st = s_t + slot * C::NE;
+      const T* sa = s_a + partner * C::NE;
       const bool direct = w <= partner;
-      // operands of K-step s4 for the eight points, loaded one step ahead
-      float xa[2][C::TP], xb[2][C::TP];
+      // operands of K-step s4 for the TP points, loaded one step ahead
+      T xa[2][TP], xb[2][TP];
 #pragma unroll
       for (int s4 = 0; s4 < 5; ++s4) {
         if (s4 < 4) {
-          const float* pa = st + (r == 7 ? oa_r[s4] : direct ? oa_d[s4] : oa_t[s4]);
-          const float* pb = sa + oa_t[s4];
+          const T* pa = st + (r == 7 ? oa_r[s4] : direct ? oa_d[s4] : oa_t[s4]);
+          const T* pb = sa + oa_t[s4];
 #pragma unroll
-          for (int p = 0; p < C::TP; ++p) {
+          for (int p = 0; p < TP; ++p) {
             xa[s4 & 1][p] = pa[p * C::PS];
             xb[s4 & 1][p] = pb[p * C::PS];
           }
         }
         if (s4 > 0) {
 #pragma unroll
-          for (int p = 0; p < C::TP; ++p)
-            acc[p] = Mfma<float>::run(xa[(s4 - 1) & 1][p], xb[(s4 - 1) & 1][p], acc[p]);
+          for (int p = 0; p < TP; ++p)
+            acc[p] = Mfma<T>::run(xa[(s4 - 1) & 1][p], xb[(s4 - 1) & 1][p], acc[p]);
         }
       }
     }
@@ -693,22 +703,23 @@ k_contract_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__
 
   // R[b][16 w + row] = -alpha acc (+ c_K phi (v_H + f_xc drho)), staged through LDS
   __syncthreads();
-  float* so = s_t + w * C::NE;
+  T* so = s_t + w * C::NE;
 #pragma unroll
-  for (int p = 0; p < C::TP; ++p)
+  for (int p = 0; p < TP; ++p)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) so[C::at(Mfma<float>::row(lane, e) * 16 + lx, p)] = acc[p][e];
+    for (int e = 0; e < 4; ++e) so[C::at(Mfma<T>::row(lane, e) * 16 + lx, p)] = acc[p][e];
   __syncthreads();
   if (!bin) return;
-  const rr_f4 vb_resp = vhb + fx * drb;
+  const V vb_resp = vhb + fx * drb;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int v = (t >> 5) + 16 * j;
-    const float* src = s_t + (v >> 4) * C::NE + C::at((v & 15) * 16 + bl, 4 * h);
-    rr_f4 val = {-alpha * src[0], -alpha * src[C::PS], -alpha * src[2 * C::PS],
-                 -alpha * src[3 * C::PS]};
+    const T* src = s_t + (v >> 4) * C::NE + C::at((v & 15) * 16 + bl, EPL * h);
+    V val;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) val[e] = -alpha * src[e * C::PS];
     if (k1e) val += ck * ph[j] * vb_resp;
-    *reinterpret_cast<rr_f4*>(R + ((int64_t)(b0 + bl) * nocc + v) * nr + rq) = val;
+    *reinterpret_cast<V*>(R + ((int64_t)(b0 + bl) * nocc + v) * nr + rq) = val;
   }
 }
 
@@ -882,7 +893,9 @@ template <typename T>
 bool contract_rr_applies(const Geometry& g, int nb, int nocc) {
   // any trial count: a ragged last tile of trials is zero-padded in the kernel,
   // so the pair-potential layout of a context does not depend on nb
-  return sizeof(T) == 4 && nocc == 128 && nb >= 1 && g.nr % RRTile::TP == 0;
+  // 16-byte loads of whole point runs: N_r a multiple of 8 (FP32 reads 8
+  // points per workgroup, FP64 4, both in 16-byte vectors)
+  return nocc == 128 && nb >= 1 && g.nr % 8 == 0;
 }
 
 template <typename T>
@@ -893,19 +906,15 @@ bool launch_contract_mfma(const Geometry& g, int nb, int nocc, const T* phi, con
   if (nt > 8) return false;
   WTD_REQUIRE(!tau_il || contract_rr_applies<T>(g, nb, nocc), WTD_ERR_SHAPE,
               "tile-ordered pair potentials need the round-robin contraction");
-  if constexpr (sizeof(T) == 4) {
-    if (tau_il) {
-      const int64_t nt64 = g.nr / RRTile::TP;
-      WTD_REQUIRE(nt64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
-      const int ntile = (int)nt64;
-      dim3 grid(8 * ((ntile + 7) / 8), (nb + 15) / 16);
-      hipLaunchKernelGGL(k_contract_rr, grid, dim3(RRTile::THREADS), 0, s, nb, nocc, g.nr, ntile,
-                         (const float*)phi, (const float*)at, (const float*)tau, (const float*)vh,
-                         (const float*)drho, (const float*)fxc, (float)ck, (float)alpha, (int)k1e,
-                         (int)k1d, (float*)R);
-      WTD_HIP(hipGetLastError());
-      return true;
-    }
+  if (tau_il) {
+    const int64_t nt64 = g.nr / RRTile<T>::TP;
+    WTD_REQUIRE(nt64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
+    const int ntile = (int)nt64;
+    dim3 grid(8 * ((ntile + 7) / 8), (nb + 15) / 16);
+    hipLaunchKernelGGL(k_contract_rr<T>, grid, dim3(RRTile<T>::THREADS), 0, s, nb, nocc, g.nr,
+                       ntile, phi, at, tau, vh, drho, fxc, ck, alpha, (int)k1e, (int)k1d, R);
+    WTD_HIP(hipGetLastError());
+    return true;
   }
   typedef CTile<T> C;
   const int64_t ntile64 = (g.nr + C::TP - 1) / C::TP;
@@ -1051,7 +1060,12 @@ __device__ __forceinline__ constexpr int br_tile_j(int n) {
   return i + n;
 }
 
-template <bool DIAG>
+// tau tiles in flight ahead of the current one (8 measured 1-3 % faster than 3
+// on 96^3 and 108^3 systems: the kernel moves its trial fields and R
+// read-modify-write, three quarters of its traffic, near the bandwidth limit)
+constexpr int kBRDepth = 8;
+
+template <bool DIAG, int PD>
 __global__ void __launch_bounds__(BRTile::THREADS)
 k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ at,
                     const float* __restrict__ tau, BArgs bk, float alpha,
@@ -1060,7 +1074,6 @@ k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __rest
   constexpr int NS = DIAG ? 1 : 2;  // row blocks with accumulators: A (and B)
   constexpr int NRT = 4 * NS;       // row tiles of a and R the workgroup touches
   constexpr int NTILE = DIAG ? 10 : 16;
-  constexpr int PD = 3;             // tau tiles in flight ahead of the current one
   __shared__ float s_a[2 * BRTile::NE];
   __shared__ float s_t[2][BRTile::NE];
   const int per = (ntile + 7) / 8;
@@ -1217,11 +1230,11 @@ void launch_contract_block_rr(const Geometry& g, int nb, int nocc, const T* at, 
     dim3 grid(8 * per, (nb + 31) / 32);
     BArgs bk{A0, nA, B0, nB, diag ? 1 : 0};
     if (diag)
-      hipLaunchKernelGGL(k_contract_block_rr<true>, grid, dim3(BRTile::THREADS), 0, s, nb, nocc,
-                         g.nr, ntile, at, tau, bk, alpha, R);
+      hipLaunchKernelGGL((k_contract_block_rr<true, kBRDepth>), grid, dim3(BRTile::THREADS), 0, s,
+                         nb, nocc, g.nr, ntile, at, tau, bk, alpha, R);
     else
-      hipLaunchKernelGGL(k_contract_block_rr<false>, grid, dim3(BRTile::THREADS), 0, s, nb, nocc,
-                         g.nr, ntile, at, tau, bk, alpha, R);
+      hipLaunchKernelGGL((k_contract_block_rr<false, kBRDepth>), grid, dim3(BRTile::THREADS), 0, s,
+                         nb, nocc, g.nr, ntile, at, tau, bk, alpha, R);
     WTD_HIP(hipGetLastError());
   }
 }
