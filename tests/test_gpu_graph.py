@@ -44,6 +44,19 @@ def test_graph_replay_matches_eager(systems, cfg, prec):
             a_out.zero_()
         graph.replay()
         torch.cuda.synchronize()
+        if not torch.equal(a_out, eager[k]):
+            # where the replay differs, and whether a second replay on the same
+            # input gives the same result
+            d = (a_out - eager[k]).abs()
+            bad = (d > 0).nonzero()
+            first = a_out.clone()
+            graph.replay()
+            torch.cuda.synchronize()
+            say(f"  replay {rep}: {bad.shape[0]} elements differ, max |d| {d.max().item():.3e} "
+                f"(|ref| max {eager[k].abs().max().item():.3e}); trials "
+                f"{sorted(set(bad[:, 0].tolist()))[:16]}, orbitals "
+                f"{sorted(set(bad[:, 1].tolist()))[:16]}; second replay equal to the first: "
+                f"{torch.equal(a_out, first)}, to the eager apply: {torch.equal(a_out, eager[k])}")
         assert torch.equal(a_out, eager[k]), f"replay {rep} differs from the eager apply"
         # eager work on the same context between replays
         with torch.cuda.stream(st):
