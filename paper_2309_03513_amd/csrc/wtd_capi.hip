@@ -563,7 +563,9 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
                 "WTD_ROW_BLOCK must be 0, 16, 32, 48 or 64");
     if (rb > 0) c->row_block = rb;
   }
-  c->tile_pairs = c->row_block == 0 && contract_rr_applies<T>(c->g, mnb, nocc);
+  // (planes too large for LDS run the register-quad kernels, which write
+  // [pair][N_r] fields only)
+  c->tile_pairs = c->row_block == 0 && c->g.quad_sn == 0 && contract_rr_applies<T>(c->g, mnb, nocc);
   {
     std::vector<int2> pr;
     std::vector<int> pidx;

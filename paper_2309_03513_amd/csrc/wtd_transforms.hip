@@ -889,6 +889,96 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
   }
 }
 
+// Density sticks -> pair potentials in the 4-pair interleaved layout, for
+// compile-time planes: the workgroup of item (plane i0, group q) transforms
+// packs 2q and 2q + 1 (the four fields of interleave group q) one after the
+// other, keeps the first plane in registers and writes the four values of a
+// point as one vector (16 bytes in FP32), so every store of a wave covers whole
+// lines; the second pack's first stick rounds load during the first transform.
+template <int MB1, int MB2, int SN, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_dsticks_to_groups(const cplx<T>* __restrict__ dst, int npack, int nfield, int n0, int n1,
+                    int n2, int nd, int nds, const int* __restrict__ k12, FFTPlan P1, FFTPlan P2,
+                    const cplx<T>* __restrict__ tw1, const cplx<T>* __restrict__ tw2,
+                    T* __restrict__ out) {
+  static_assert(SN > 0 && kTauIl == 4, "compile-time planes, 4-pair groups");
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int PL = SN * SN;
+  constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
+  constexpr int KR = stick_regs<SN>();
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* twl = pl + PL;
+  const int ngrp = (npack + 1) / 2;
+  const int item = xcd_item(n0 * ngrp);
+  if (item < 0) return;
+  stage_twiddles<SN>(twl, tw1);
+  const int i0 = item / ngrp;
+  const int q = item - i0 * ngrp;
+  const int64_t nr = (int64_t)n0 * PL;
+  const bool two = 2 * q + 1 < npack;
+  int kp[KR];
+  cplx<T> sv[KR];
+  auto load = [&](int pack) {
+    const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+#pragma unroll
+    for (int e = 0; e < KR; ++e) {
+      const int st = threadIdx.x + e * kPlaneThreads;
+      sv[e] = kp[e] >= 0 ? src[st] : cplx<T>{T(0), T(0)};
+    }
+  };
+  // fill the plane with pack `pack` (registers sv for the first rounds)
+  auto fill = [&](int pack) {
+    for (int i = threadIdx.x; i < PL; i += blockDim.x) pl[i] = {T(0), T(0)};
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < KR; ++e)
+      if (kp[e] >= 0) pl[kp[e]] = sv[e];
+    const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+    for (int st = threadIdx.x + KR * kPlaneThreads; st < nd; st += blockDim.x)
+      pl[k12[st]] = src[st];
+    __syncthreads();
+  };
+#pragma unroll
+  for (int e = 0; e < KR; ++e) {
+    const int st = threadIdx.x + e * kPlaneThreads;
+    kp[e] = st < nd ? k12[st] : -1;
+  }
+  load(2 * q);
+  fill(2 * q);
+  if (two) load(2 * q + 1);
+  plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+  cplx<T> keep[EL];
+#pragma unroll
+  for (int e = 0; e < EL; ++e) {
+    const int i = threadIdx.x + e * kPlaneThreads;
+    if (PL % kPlaneThreads == 0 || i < PL) keep[e] = pl[i];
+  }
+  __syncthreads();
+  if (two) {
+    fill(2 * q + 1);
+    plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+  }
+  // group q holds fields 4q .. 4q + 3 (those below nfield exist)
+  T* o = out + ((int64_t)q * nr + (int64_t)i0 * PL) * 4;
+  const int f0 = 4 * q;
+  const bool full = f0 + 3 < nfield;
+#pragma unroll
+  for (int e = 0; e < EL; ++e) {
+    const int i = threadIdx.x + e * kPlaneThreads;
+    if (PL % kPlaneThreads == 0 || i < PL) {
+      const cplx<T> b = two ? pl[i] : cplx<T>{T(0), T(0)};
+      if (full) {
+        *reinterpret_cast<v4*>(o + 4 * (int64_t)i) = v4{keep[e].x, keep[e].y, b.x, b.y};
+      } else {
+        o[4 * (int64_t)i] = keep[e].x;
+        if (f0 + 1 < nfield) o[4 * (int64_t)i + 1] = keep[e].y;
+        if (f0 + 2 < nfield) o[4 * (int64_t)i + 2] = b.x;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- K2d: inverse pass + contraction
 // Pack p = j (nocc / 2) + k of dst holds the Poisson-solved products a_bv' phi_v
 // and a_bv' phi_v+1 (v' = r0 + j, v = 2k) on density sticks.  The workgroup of
@@ -1331,6 +1421,21 @@ int plane_static(const Geometry& g) { return g.n1 == g.n2 ? static_size(g.n1) : 
 #define WTD_PLANE_LAUNCH(K, T, grid, lds0, stream, ...) \
   WTD_PLANE_LAUNCH_SN(plane_static(g), K, T, grid, lds0, stream, __VA_ARGS__)
 
+// the same for kernels that exist for compile-time planes only
+#define WTD_PLANE_LAUNCH_STATIC(K, T, grid, lds0, stream, ...)                           \
+  do {                                                                                  \
+    switch (plane_static(g)) {                                                          \
+      WTD_PLANE_CASE(48, K, T, grid, lds0, stream, __VA_ARGS__)                         \
+      WTD_PLANE_CASE(60, K, T, grid, lds0, stream, __VA_ARGS__)                         \
+      WTD_PLANE_CASE(72, K, T, grid, lds0, stream, __VA_ARGS__)                         \
+      WTD_PLANE_CASE(96, K, T, grid, lds0, stream, __VA_ARGS__)                         \
+      WTD_PLANE_CASE(108, K, T, grid, lds0, stream, __VA_ARGS__)                        \
+      default:                                                                          \
+        throw StatusError{WTD_ERR_SHAPE, "plane size without a compile-time FFT plan"}; \
+    }                                                                                   \
+    WTD_HIP(hipGetLastError());                                                         \
+  } while (0)
+
 // static size for the wave-stick plane kernels, which keep the wave sticks of
 // an item in wave_stick_regs<SN>() registers per thread (runtime plans where
 // the sphere has more sticks than that holds)
@@ -1453,6 +1558,16 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
   if (g.quad_sn > 0 && !il) {
     WTD_QUAD_LAUNCH(k_dsticks_to_fields_q, T, g.ndrow, g.n0 * npack, s, dst, npack, nfield, g.n0,
                     g.nds, g.ndrow, g.drows, out);
+    return;
+  }
+  if (il && plane_static(g) > 0) {
+    const int ngrp = (npack + 1) / 2;
+    dim3 grid((unsigned)((g.n0 * ngrp + 7) / 8 * 8));
+    const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
+    WTD_PLANE_LAUNCH_STATIC(k_dsticks_to_groups, T, grid, lds, s, dst, npack, nfield, g.n0, g.n1,
+                            g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2,
+                            static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2),
+                            out);
     return;
   }
   dim3 grid((unsigned)((g.n0 * npack + 7) / 8 * 8));
