@@ -34,51 +34,59 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 876.7e6,
+        "bytes": 737.7e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "a7003785add808e91a1d17ad03add473366802e8d267687db944d89ae4f4535f",
+                "9a347e907745673a4a896dd61f98393f3ae528f23adc6979360b0b9291ea1a89",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
             "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
                 "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
+            "paper_2309_03513_amd/csrc/wtd_internal.h":
+                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1295.0e6,
+        "bytes": 1294.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "a7003785add808e91a1d17ad03add473366802e8d267687db944d89ae4f4535f",
+                "9a347e907745673a4a896dd61f98393f3ae528f23adc6979360b0b9291ea1a89",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
             "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
                 "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
+            "paper_2309_03513_amd/csrc/wtd_internal.h":
+                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
         },
     },
     "pair_plane_inv": {
-        "bytes": 1983.3e6,
+        "bytes": 1983.0e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "a7003785add808e91a1d17ad03add473366802e8d267687db944d89ae4f4535f",
+                "9a347e907745673a4a896dd61f98393f3ae528f23adc6979360b0b9291ea1a89",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
                 "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
             "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
                 "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
+            "paper_2309_03513_amd/csrc/wtd_internal.h":
+                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
         },
     },
     "contract": {
-        "bytes": 19723.8e6,
+        "bytes": 18785.9e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "845471063d7740dbee2ad66337f66b6d18ca4630b57c029aa96fcd35fc041773",
+                "1bac15395d1af00ebff6ab62254ff4c43e287f49d847c2623fc29ebbf5cc2e2b",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
+            "paper_2309_03513_amd/csrc/wtd_internal.h":
+                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
         },
     },
 }
