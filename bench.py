@@ -276,8 +276,12 @@ def run_batch(steps, warmup):
         "sequential": {"value": total_nb / t_seq, "ms_per_step": t_seq * 1e3},
         "graphs": {"value": total_nb / t_graph, "ms_per_step": t_graph * 1e3},
         "workspace_GiB": ws / 2**30,
+        # model_frac: the path's byte model (model_bytes) per apply / time alone / 8 TB/s
         "systems": [{"name": c.name, "grid": c.n[0], "nocc": c.nocc, "nb": c.nb,
-                     "ms_alone": round(t, 3)} for c, t in zip(cfgs, per_sys)],
+                     "ms_alone": round(t, 3),
+                     "model_frac": round(model_bytes(sy, c.nb, 4) / (t * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS, 3)}
+                    for c, sy, t in zip(cfgs, systems, per_sys)],
     }
     del graphs
     for L in ctxs:

@@ -994,13 +994,15 @@ void launch_contract_block(const Geometry& g, int nb, int nocc, const T* at, con
 namespace {
 // ---------------------------------------------------------------------------
 // Row-blocked contraction, FP32, trial fields in registers.  A workgroup owns 8
-// grid points (one per wave) and 32 trials of one block pair (A, B): every wave
-// first takes the MFMA operand fragments of a[A] and a[B] (16 x 16 tiles, both
-// trial tiles) for its point into registers, then walks the block's tau tiles
-// once, staged through LDS with the next tile's loads in flight, and adds
+// grid points (one per wave) and 16 NT trials of one block pair (A, B): every
+// wave first takes the MFMA operand fragments of a[A] and a[B] (16 x 16 tiles,
+// NT trial tiles) for its point into registers, then walks the block's tau
+// tiles once, staged through LDS with the next tiles' loads in flight, and adds
 // R[A] += tau a[B] and R[B] += tau^T a[A] (upper-triangle tiles and
 // R[A] += tau a[A] on the diagonal block) into accumulators that are written
-// back once: tau is read once for all trials and a once per block pair.
+// back once: tau is read once per 16 NT trials and a once per block pair.
+// Launched with NT = 1: with half the registers of NT = 2, two workgroups
+// share a CU, which outweighs reading tau once per 16 trials instead of 32.
 // tau is in the 4-pair interleaved layout: block-local pair P at point r is
 // element ((P / 4) N_r + r) 4 + P % 4.
 struct BRTile {
@@ -1060,13 +1062,15 @@ __device__ __forceinline__ constexpr int br_tile_j(int n) {
   return i + n;
 }
 
-// tau tiles in flight ahead of the current one (8 measured 1-3 % faster than 3
-// on 96^3 and 108^3 systems: the kernel moves its trial fields and R
-// read-modify-write, three quarters of its traffic, near the bandwidth limit)
-constexpr int kBRDepth = 8;
+// tau tiles in flight ahead of the current one; the 16-trial workgroup is held
+// to 128 VGPRs (two workgroups per CU), where four tiles spill 12 bytes per lane
+// and still measured fastest (contraction per 108^3 / Nb = 32 apply: 3, 4, 5 and
+// 6 tiles 697, 646, 648 and 662 ms)
+constexpr int kBRDepth = 4;
 
-template <bool DIAG, int PD>
+template <bool DIAG, int PD, int NT>
 __global__ void __launch_bounds__(BRTile::THREADS)
+__attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 1)))
 k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __restrict__ at,
                     const float* __restrict__ tau, BArgs bk, float alpha,
                     float* __restrict__ R) {
@@ -1074,60 +1078,63 @@ k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __rest
   constexpr int NS = DIAG ? 1 : 2;  // row blocks with accumulators: A (and B)
   constexpr int NRT = 4 * NS;       // row tiles of a and R the workgroup touches
   constexpr int NTILE = DIAG ? 10 : 16;
-  __shared__ float s_a[2 * BRTile::NE];
+  __shared__ float s_a[NT * BRTile::NE];
   __shared__ float s_t[2][BRTile::NE];
   const int per = (ntile + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntile) return;
-  const int b0 = blockIdx.y * 32;
+  const int b0 = blockIdx.y * 16 * NT;
   const int64_t r0 = (int64_t)tile * BRTile::TP;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lx = lane & 15, ly = lane >> 4;
   const int base[2] = {bk.A0, DIAG ? bk.A0 : bk.B0};
   const int nrow[2] = {bk.nA, DIAG ? bk.nA : bk.nB};
-  // element u of this thread in a 16-row x 32-trial x 8-point slab of a or R
+  // element u of this thread in a 16-row x 16 NT-trial x 8-point slab of a or R
+  constexpr int NBT = 16 * NT;               // trials per workgroup
+  constexpr int SU = 16 * NBT * 8 / BRTile::THREADS;  // slab elements per thread
+  constexpr int RS = NT == 2 ? 8 : 7;        // log2(trials x points) of one slab row
   auto slab_ok = [&](int rt, int u) {
     const int e = threadIdx.x + u * BRTile::THREADS;
-    const int sd = rt >> 2, v = (rt & 3) * 16 + (e >> 8);
-    return v < nrow[sd] && b0 + ((e >> 3) & 31) < nb && r0 + (e & 7) < nr;
+    const int sd = rt >> 2, v = (rt & 3) * 16 + (e >> RS);
+    return v < nrow[sd] && b0 + ((e >> 3) & (NBT - 1)) < nb && r0 + (e & 7) < nr;
   };
   auto slab_off = [&](int rt, int u) {
     const int e = threadIdx.x + u * BRTile::THREADS;
-    const int sd = rt >> 2, v = (rt & 3) * 16 + (e >> 8);
-    return ((int64_t)(b0 + ((e >> 3) & 31)) * nocc + base[sd] + v) * nr + r0 + (e & 7);
+    const int sd = rt >> 2, v = (rt & 3) * 16 + (e >> RS);
+    return ((int64_t)(b0 + ((e >> 3) & (NBT - 1))) * nocc + base[sd] + v) * nr + r0 + (e & 7);
   };
   auto slab_lds = [&](int u) {
     const int e = threadIdx.x + u * BRTile::THREADS;
-    const int b = (e >> 3) & 31;
-    return (b >> 4) * BRTile::NE + BRTile::at((e >> 8) * 16 + (b & 15), e & 7);
+    const int b = (e >> 3) & (NBT - 1);
+    return (b >> 4) * BRTile::NE + BRTile::at((e >> RS) * 16 + (b & 15), e & 7);
   };
 
   // 1. every a load of the workgroup in flight at once, then the operand
   // fragments y[row tile][trial tile][k] = a[row 4k + ly][trial lx] per wave
-  float la[NRT][8];
+  float la[NRT][SU];
 #pragma unroll
   for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) la[rt][u] = slab_ok(rt, u) ? at[slab_off(rt, u)] : 0.f;
-  float y[NRT][2][4];
+    for (int u = 0; u < SU; ++u) la[rt][u] = slab_ok(rt, u) ? at[slab_off(rt, u)] : 0.f;
+  float y[NRT][NT][4];
 #pragma unroll
   for (int rt = 0; rt < NRT; ++rt) {
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s_a[slab_lds(u)] = la[rt][u];
+    for (int u = 0; u < SU; ++u) s_a[slab_lds(u)] = la[rt][u];
     __syncthreads();
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         y[rt][tt][k] = s_a[tt * BRTile::NE + BRTile::at((4 * k + ly) * 16 + lx, wave)];
   }
 
-  acc_t acc[NRT][2];
+  acc_t acc[NRT][NT];
 #pragma unroll
   for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) acc[rt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
+    for (int tt = 0; tt < NT; ++tt) acc[rt][tt] = acc_t{0.f, 0.f, 0.f, 0.f};
 
   // 2. tau tiles, PD tiles of loads in flight, staged through two LDS buffers
   float pf[PD][4];
@@ -1152,7 +1159,7 @@ k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __rest
       xt[k] = st[BRTile::at((4 * k + ly) * 16 + lx, wave)];
     }
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
+    for (int tt = 0; tt < NT; ++tt) {
       // R[A]_I += tau_IJ a[B]_J  (a[A]_J on the diagonal block)
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -1171,20 +1178,20 @@ k_contract_block_rr(int nb, int nocc, int64_t nr, int ntile, const float* __rest
 #pragma unroll
   for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) la[rt][u] = slab_ok(rt, u) ? R[slab_off(rt, u)] : 0.f;
+    for (int u = 0; u < SU; ++u) la[rt][u] = slab_ok(rt, u) ? R[slab_off(rt, u)] : 0.f;
 #pragma unroll
   for (int rt = 0; rt < NRT; ++rt) {
     if ((rt & 3) * 16 >= nrow[rt >> 2]) continue;
     __syncthreads();
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         s_a[tt * BRTile::NE + BRTile::at(Mfma<float>::row(lane, e) * 16 + lx, wave)] =
             acc[rt][tt][e];
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < SU; ++u)
       if (slab_ok(rt, u)) R[slab_off(rt, u)] = la[rt][u] - alpha * s_a[slab_lds(u)];
   }
 }
@@ -1227,14 +1234,18 @@ void launch_contract_block_rr(const Geometry& g, int nb, int nocc, const T* at, 
     WTD_REQUIRE(ntile64 < (1ll << 30), WTD_ERR_SHAPE, "contraction grid too large");
     const int ntile = (int)ntile64;
     const int per = (ntile + 7) / 8;
-    dim3 grid(8 * per, (nb + 31) / 32);
     BArgs bk{A0, nA, B0, nB, diag ? 1 : 0};
+    // 16 trials per workgroup: half the registers of a 32-trial workgroup, so
+    // two workgroups share a CU and one's loads overlap the other's MFMA work
+    // (faster even where tau is then read once per 16 trials: 108^3 / Nb = 32
+    // 1,748 -> 1,612 ms per apply; 96^3 / Nb = 10 272 -> 209 ms)
+    dim3 grid(8 * per, (nb + 15) / 16);
     if (diag)
-      hipLaunchKernelGGL((k_contract_block_rr<true, kBRDepth>), grid, dim3(BRTile::THREADS), 0, s,
-                         nb, nocc, g.nr, ntile, at, tau, bk, alpha, R);
+      hipLaunchKernelGGL((k_contract_block_rr<true, kBRDepth, 1>), grid, dim3(BRTile::THREADS), 0,
+                         s, nb, nocc, g.nr, ntile, at, tau, bk, alpha, R);
     else
-      hipLaunchKernelGGL((k_contract_block_rr<false, kBRDepth>), grid, dim3(BRTile::THREADS), 0, s,
-                         nb, nocc, g.nr, ntile, at, tau, bk, alpha, R);
+      hipLaunchKernelGGL((k_contract_block_rr<false, kBRDepth, 1>), grid, dim3(BRTile::THREADS), 0,
+                         s, nb, nocc, g.nr, ntile, at, tau, bk, alpha, R);
     WTD_HIP(hipGetLastError());
   }
 }

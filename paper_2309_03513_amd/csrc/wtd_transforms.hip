@@ -1560,7 +1560,9 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
                     g.nds, g.ndrow, g.drows, out);
     return;
   }
-  if (il && plane_static(g) > 0) {
+  // (not on 96 x 96 planes: the kept plane takes the group kernel above 128
+  // VGPRs, one workgroup per CU where the LDS holds two)
+  if (il && plane_static(g) > 0 && plane_static(g) != 96) {
     const int ngrp = (npack + 1) / 2;
     dim3 grid((unsigned)((g.n0 * ngrp + 7) / 8 * 8));
     const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
