@@ -284,6 +284,7 @@ void prof_finish(wtd_ctx* c) {
 FFTPlan make_plan(int n) {
   FFTPlan P{};
   P.n = n;
+  P.cut = -1;
   int rem = n, np = 0, prod = 1;
   const int order[] = {8, 5, 4, 3, 2};
   while (rem > 1) {
@@ -430,9 +431,10 @@ void build_geometry(wtd_ctx* c, const wtd_system* sys) {
   upload(c, d_dk, dk12);
   g.dst_k12 = d_dk;
   // rows of the stick sets for the register-quad plane kernels
-  auto stick_rows = [&](const std::vector<int>& k12, int& nrow, const int4*& dev) {
+  auto stick_rows = [&](const std::vector<int>& k12, int& nrow, const int4*& dev, int& rmax) {
     std::vector<int4> rows;
     bool regular = true;
+    rmax = -1;
     const int ns = (int)k12.size();
     for (int s0 = 0; s0 < ns;) {
       const int k1 = k12[s0] / n[2];
@@ -443,16 +445,28 @@ void build_geometry(wtd_ctx* c, const wtd_system* sys) {
       for (int i = 0; ok && i < cnt; ++i)
         ok = k12[s0 + i] % n[2] == (i <= R ? i : n[2] - (cnt - i));
       regular = regular && ok;
+      rmax = std::max(rmax, R);
       rows.push_back(int4{k1, s0, R, 0});
       s0 = s1;
     }
     nrow = regular ? (int)rows.size() : 0;
+    if (!regular) rmax = -1;
     int4* d = (int4*)dalloc(c, std::max<size_t>(rows.size(), 1) * sizeof(int4));
     if (!rows.empty()) h2d(c, d, rows.data(), rows.size() * sizeof(int4));
     dev = d;
   };
-  stick_rows(dk12, g.ndrow, g.drows);
-  stick_rows(wk12, g.nwrow, g.wrows);
+  int dcut = -1, wcut = -1;
+  stick_rows(dk12, g.ndrow, g.drows, dcut);
+  stick_rows(wk12, g.nwrow, g.wrows, wcut);
+  // column passes of the density- and wave-stick plane kernels: only the
+  // columns k2 their stick rows reach (every column if the rows are irregular
+  // or the plane is not square)
+  g.plan1d = g.plan1;
+  g.plan1w = g.plan1;
+  if (g.n1 == g.n2) {
+    g.plan1d.cut = (dcut >= 0 && 2 * dcut + 1 < g.n2) ? dcut : -1;
+    g.plan1w.cut = (wcut >= 0 && 2 * wcut + 1 < g.n2) ? wcut : -1;
+  }
   {
     const char* e = std::getenv("WTD_QUAD_PLANES");
     g.quad_sn = quad_plane_size(g, sizeof(T), e && std::atoi(e) != 0);

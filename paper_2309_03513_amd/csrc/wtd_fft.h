@@ -54,6 +54,10 @@ struct FFTPlan {
   int np;
   int rad[kMaxPasses];
   int p[kMaxPasses];
+  // compile-time plane passes along this axis: transform only the lines
+  // (columns k2) 0..cut and n2 - cut..n2 - 1, the ones a stick set reaches
+  // (-1: every line)
+  int cut;
 };
 
 // r-point DFTs with sign S on v[0..r-1] (in place).

@@ -137,4 +137,80 @@ __device__ __forceinline__ void ct_fft(cplx<T>* buf, const cplx<T>* tw) {
   ct_pass<S, N, NL, ES, LS, NTHR, LF, 0>(buf, tw);
 }
 
+// The column passes of an N x N plane [k1][k2] restricted to the nl = 2 cut + 1
+// columns k2 = 0..cut and N - cut..N - 1: consecutive threads take consecutive
+// columns of that set; butterfly b is (column slot b mod nl, index b / nl),
+// with the quotient from a float product that is exact here (b < 2^13,
+// nl < 128: the fraction of (b + 1/2) / nl stays at least 1 / (2 nl) away
+// from an integer, far beyond the product's rounding).
+template <int S, int N, int NTHR, int PASS, typename T>
+__device__ __forceinline__ void ct_pass_cols(cplx<T>* buf, const cplx<T>* tw, int nl, int cut,
+                                             float inv_nl) {
+  if constexpr (PASS < ct_greedy_count(N)) {
+    constexpr int R = ct_radix(N, PASS);
+    constexpr int P = ct_prod(N, PASS);
+    constexpr int M = N / R;
+    constexpr int TWS = N / (P * R);
+    constexpr int UB = (N * M + NTHR - 1) / NTHR;
+    static_assert(N * M < (1 << 13) && N < 128, "exact quotient by a float product");
+    const int B = nl * M;
+    const int tid = threadIdx.x;
+    cplx<T> v[UB][R];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int b = tid + u * NTHR;
+      if (b < B) {
+        const int i = (int)(((float)b + 0.5f) * inv_nl);
+        const int slot = b - i * nl;
+        const int col = slot <= cut ? slot : slot + (N - nl);
+        const int k = i % P;
+        cplx<T>* base = buf + col;
+        cplx<T> wp[R];
+        if constexpr (P > 1) {
+          wp[1] = tw[k * TWS];
+          if constexpr (R > 2) wp[2] = tw[2 * k * TWS];
+#pragma unroll
+          for (int t = 3; t < R; ++t) wp[t] = cmul(wp[t / 2], wp[t - t / 2]);
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          cplx<T> x = base[(i + t * M) * N];
+          if (P > 1 && t > 0) x = (S < 0) ? cmul(x, wp[t]) : cmulc(x, wp[t]);
+          v[u][t] = x;
+        }
+        ct_dft<R, S>(v[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int b = tid + u * NTHR;
+      if (b < B) {
+        const int i = (int)(((float)b + 0.5f) * inv_nl);
+        const int slot = b - i * nl;
+        const int col = slot <= cut ? slot : slot + (N - nl);
+        const int k = i % P;
+        const int j0 = (i - k) * R + k;
+        cplx<T>* base = buf + col;
+#pragma unroll
+        for (int q = 0; q < R; ++q) base[(j0 + q * P) * N] = v[u][q];
+      }
+    }
+    __syncthreads();
+    ct_pass_cols<S, N, NTHR, PASS + 1>(buf, tw, nl, cut, inv_nl);
+  }
+}
+
+// Column passes of an N x N plane: every column (cut < 0) or the 2 cut + 1 a
+// stick set reaches.
+template <int S, int N, int NTHR, typename T>
+__device__ __forceinline__ void ct_fft_cols(cplx<T>* buf, const cplx<T>* tw, int cut) {
+  if (cut < 0) {
+    ct_fft<S, N, N, N, 1, NTHR, true>(buf, tw);
+  } else {
+    const int nl = 2 * cut + 1;
+    ct_pass_cols<S, N, NTHR, 0>(buf, tw, nl, cut, 1.0f / (float)nl);
+  }
+}
+
 }  // namespace wtd

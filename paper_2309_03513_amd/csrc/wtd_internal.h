@@ -39,6 +39,9 @@ struct Geometry {
   int plane;       // n1*n2
   double omega;
   FFTPlan plan0, plan1, plan2;
+  // plan1 with the column cut of the density sticks and of the wave sticks
+  // (the column pass of the compile-time plane kernels; see FFTPlan::cut)
+  FFTPlan plan1d, plan1w;
   // twiddle tables (one per axis), device, working precision
   const void* tw0;
   const void* tw1;

@@ -74,17 +74,20 @@ int pick_maxb(int nlines, const FFTPlan& p, int nthreads) {
 
 // 2D FFT of the LDS plane [k1][k2] (k2 fastest): S = -1 rows first then columns
 // (forward), S = +1 columns first then rows (inverse).  SN > 0: n1 = n2 = SN with
-// a compile-time plan and the twiddle table `twl` in LDS; SN = 0: runtime plans.
+// a compile-time plan and the twiddle table `twl` in LDS, the column pass on
+// the columns of P1.cut only; SN = 0: runtime plans, every column.
 template <int S, int SN, int MB1, int MB2, typename T>
 __device__ __forceinline__ void plane_fft(cplx<T>* pl, const FFTPlan& P1, const FFTPlan& P2,
                                           int n1, int n2, const cplx<T>* tw1,
                                           const cplx<T>* tw2, const cplx<T>* twl) {
   if constexpr (SN > 0) {
+    // the columns outside P1.cut hold nothing the caller reads (forward) or
+    // only zeros (inverse)
     if (S < 0) {
       ct_fft<S, SN, SN, 1, SN, kPlaneThreads, false>(pl, twl);
-      ct_fft<S, SN, SN, SN, 1, kPlaneThreads, true>(pl, twl);
+      ct_fft_cols<S, SN, kPlaneThreads>(pl, twl, P1.cut);
     } else {
-      ct_fft<S, SN, SN, SN, 1, kPlaneThreads, true>(pl, twl);
+      ct_fft_cols<S, SN, kPlaneThreads>(pl, twl, P1.cut);
       ct_fft<S, SN, SN, 1, SN, kPlaneThreads, false>(pl, twl);
     }
   } else {
@@ -1509,7 +1512,7 @@ void launch_wsticks_to_fields(const Geometry& g, const cplx<T>* wst, int nb, int
   T* dtarget = (ngroup > 1) ? part : drho;
   WTD_PLANE_LAUNCH_SN(sn, k_wsticks_to_fields, T, grid, lds, s, wst, npt,
                       per_trial, g.n0, g.n1, g.n2,
-                   g.nw, g.nws, g.wst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   g.nw, g.nws, g.wst_k12, g.plan1w, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), scale, out, phi, dtarget, ngroup, nb);
   }
   if (ngroup > 1) {
@@ -1534,7 +1537,7 @@ void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads,
   dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_pairs_to_dsticks, T, grid, lds, s, src, quads, npack, limit, g.n0, g.n1,
-                   g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   g.n2, g.nd, g.nds, g.dst_k12, g.plan1d, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), dst);
 }
 
@@ -1567,7 +1570,7 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
     dim3 grid((unsigned)((g.n0 * ngrp + 7) / 8 * 8));
     const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
     WTD_PLANE_LAUNCH_STATIC(k_dsticks_to_groups, T, grid, lds, s, dst, npack, nfield, g.n0, g.n1,
-                            g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2,
+                            g.n2, g.nd, g.nds, g.dst_k12, g.plan1d, g.plan2,
                             static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2),
                             out);
     return;
@@ -1575,7 +1578,7 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
   dim3 grid((unsigned)((g.n0 * npack + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_dsticks_to_fields, T, grid, lds, s, dst, npack, il ? 1 : 0, nfield, g.n0,
-                   g.n1, g.n2, g.nd, g.nds, g.dst_k12, g.plan1, g.plan2,
+                   g.n1, g.n2, g.nd, g.nds, g.dst_k12, g.plan1d, g.plan2,
                    static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2), out);
 }
 
@@ -1593,7 +1596,7 @@ bool launch_k2d_inverse(const Geometry& g, const cplx<T>* dst, int nrows, int r0
   dim3 grid((unsigned)((g.n0 * (nocc / 2) + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_k2d_inverse, T, grid, lds, s, dst, nrows, r0, nocc, g.n0, g.n1, g.n2, g.nd,
-                   g.nds, g.dst_k12, g.plan1, g.plan2, static_cast<const cplx<T>*>(g.tw1),
+                   g.nds, g.dst_k12, g.plan1d, g.plan2, static_cast<const cplx<T>*>(g.tw1),
                    static_cast<const cplx<T>*>(g.tw2), phi, alpha, R);
   return true;
 }
@@ -1614,7 +1617,7 @@ void launch_fields_to_wsticks(const Geometry& g, const T* fields, int nb, int pe
   dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
   WTD_PLANE_LAUNCH(k_fields_to_wsticks, T, grid, lds, s, fields, npt, per_trial, items, g.n0,
-                   g.n1, g.n2, g.nw, g.nws, g.wst_k12, g.plan1, g.plan2,
+                   g.n1, g.n2, g.nw, g.nws, g.wst_k12, g.plan1w, g.plan2,
                    static_cast<const cplx<T>*>(g.tw1), static_cast<const cplx<T>*>(g.tw2), wst,
                    npack);
 }
