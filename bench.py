@@ -34,59 +34,59 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 737.7e6,
+        "bytes": 737.4e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "9a347e907745673a4a896dd61f98393f3ae528f23adc6979360b0b9291ea1a89",
+                "994559caaa6dce643418a5d6a72be0d62a0198e6fde70500f89bbe9f2ef153e7",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
-                "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
+                "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
-                "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+                "a554b5bdea11e3e8db23caee697246b1a739d4febc65b82769cd5140a89791e5",
             "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
                 "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
             "paper_2309_03513_amd/csrc/wtd_internal.h":
-                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
+                "a3af2bc44d99f22d717fe27f3b4ec149ef02e9250e25a3d0e1c62b3cc2a1bc6a",
         },
     },
     "pair_stick_poisson": {
         "bytes": 1294.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "9a347e907745673a4a896dd61f98393f3ae528f23adc6979360b0b9291ea1a89",
+                "994559caaa6dce643418a5d6a72be0d62a0198e6fde70500f89bbe9f2ef153e7",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
-                "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
+                "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
-                "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+                "a554b5bdea11e3e8db23caee697246b1a739d4febc65b82769cd5140a89791e5",
             "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
                 "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
             "paper_2309_03513_amd/csrc/wtd_internal.h":
-                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
+                "a3af2bc44d99f22d717fe27f3b4ec149ef02e9250e25a3d0e1c62b3cc2a1bc6a",
         },
     },
     "pair_plane_inv": {
-        "bytes": 1983.0e6,
+        "bytes": 1983.1e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "9a347e907745673a4a896dd61f98393f3ae528f23adc6979360b0b9291ea1a89",
+                "994559caaa6dce643418a5d6a72be0d62a0198e6fde70500f89bbe9f2ef153e7",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
-                "13507d9b6e1a2321abab22e60bfb70ecf4677d91258fa9a243159ef6afef9769",
+                "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
-                "baf38afb9c84704f2a88d49e8995ea3a201faadb4c77e4a83f44edda7246ef62",
+                "a554b5bdea11e3e8db23caee697246b1a739d4febc65b82769cd5140a89791e5",
             "paper_2309_03513_amd/csrc/wtd_fft_reg.h":
                 "9c3bfd302d2ab20d3774f1097417663ad40c147dcbf7f3ed1b7bffc634998b90",
             "paper_2309_03513_amd/csrc/wtd_internal.h":
-                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
+                "a3af2bc44d99f22d717fe27f3b4ec149ef02e9250e25a3d0e1c62b3cc2a1bc6a",
         },
     },
     "contract": {
-        "bytes": 18785.9e6,
+        "bytes": 18790.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
-                "1bac15395d1af00ebff6ab62254ff4c43e287f49d847c2623fc29ebbf5cc2e2b",
+                "9d1d34d88248f78ad25d8c22d0d9692e18d5333e3b766b5b52ef8faf6f76dd9f",
             "paper_2309_03513_amd/csrc/wtd_mfma.h":
                 "08e4d52584a84a30fbc8ca0b41059ef931458de71661b2f5e6752aedd453655f",
             "paper_2309_03513_amd/csrc/wtd_internal.h":
-                "29779438ef7ecfbfe0b417cf6ec006eb207c779d249f354292f28989914297bf",
+                "a3af2bc44d99f22d717fe27f3b4ec149ef02e9250e25a3d0e1c62b3cc2a1bc6a",
         },
     },
 }
