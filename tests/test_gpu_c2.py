@@ -1,7 +1,8 @@
 """Parity at the benchmark workload's full size (72^3 grid, Nocc = 128, Nb = 16).
 
 The oracle computes sampled output rows v one by one (every row needs all 128
-pair potentials of that v); eigenvalues are compared with the oracle's FP64
+pair potentials of that v), for the whole operator and for the K1d and K1e
+terms alone; eigenvalues are compared with the oracle's FP64
 Davidson roots stored in tests/golden/roots_c2.json (written by
 tests/golden/make_golden.py from the oracle alone).
 """
@@ -28,6 +29,31 @@ def c2(systems):
     say("oracle rows for the 72^3 / Nocc=128 block")
     ref = oracle.apply_liouville(s, a, rows=ROWS)
     return s, a, ref
+
+
+@pytest.fixture(scope="module")
+def c2_terms(c2):
+    """The oracle's sampled rows of the K1d and K1e terms alone (the D term
+    dominates the sum, so a K-term error could hide under it)."""
+    s, a, _ = c2
+    say("oracle K1d and K1e rows for the 72^3 / Nocc=128 block")
+    return {"k1d": oracle.apply_liouville(s, a, terms=oracle.TERM_K1D, rows=ROWS),
+            "k1e": oracle.apply_liouville(s, a, terms=oracle.TERM_K1E, rows=ROWS)}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+@pytest.mark.parametrize("term", ["k1d", "k1e"])
+def test_c2_term_rows(c2, c2_terms, prec, tol, term):
+    from paper_2309_03513_amd import Liouville
+    s, a, _ = c2
+    mask = {"k1d": oracle.TERM_K1D, "k1e": oracle.TERM_K1E}[term]
+    say(f"c2 {term} rows {ROWS} {prec}")
+    L = Liouville(s, max_nb=16, precision=prec, terms=mask)
+    got = to_complex(L.apply(a))[:, ROWS]
+    L.close()
+    err = rel_err(got, c2_terms[term])
+    say(f"  rel err {err:.3e}")
+    assert err <= tol
 
 
 def _golden():
