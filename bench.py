@@ -34,10 +34,10 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 737.4e6,
+        "bytes": 736.6e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "994559caaa6dce643418a5d6a72be0d62a0198e6fde70500f89bbe9f2ef153e7",
+                "093a1a1658daa5b3d025f5bbe0ed161e0f44e62873afc4db39adc5158b3d43ae",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -49,10 +49,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1294.8e6,
+        "bytes": 1295.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "994559caaa6dce643418a5d6a72be0d62a0198e6fde70500f89bbe9f2ef153e7",
+                "093a1a1658daa5b3d025f5bbe0ed161e0f44e62873afc4db39adc5158b3d43ae",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -67,7 +67,7 @@ MEASURED_TRAFFIC = {
         "bytes": 1983.1e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "994559caaa6dce643418a5d6a72be0d62a0198e6fde70500f89bbe9f2ef153e7",
+                "093a1a1658daa5b3d025f5bbe0ed161e0f44e62873afc4db39adc5158b3d43ae",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -79,7 +79,7 @@ MEASURED_TRAFFIC = {
         },
     },
     "contract": {
-        "bytes": 18790.8e6,
+        "bytes": 18807.4e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
                 "9d1d34d88248f78ad25d8c22d0d9692e18d5333e3b766b5b52ef8faf6f76dd9f",

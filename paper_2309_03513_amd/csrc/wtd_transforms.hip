@@ -1544,9 +1544,9 @@ void launch_pairs_to_dsticks(const Geometry& g, const T* src, const int4* quads,
 template <typename T>
 void launch_dstick_poisson(const Geometry& g, cplx<T>* dst, int npack, hipStream_t s) {
   const int ntile = (g.nd + kStickTile - 1) / kStickTile;
-  // several tiles per workgroup with prefetch pays off for FP32 (for FP64 the
-  // larger register footprint costs more occupancy than the prefetch gains)
-  const int items = (static_size(g.n0) && sizeof(T) == 4) ? kPairItems : 1;
+  // several tiles per workgroup, the next one's sticks prefetched into
+  // registers (FP64: two; 1 and 4 measured 6 and 1 % slower at 72^3)
+  const int items = static_size(g.n0) ? (sizeof(T) == 4 ? kPairItems : 2) : 1;
   const int ngrp = (ntile * npack + items - 1) / items;
   dim3 grid((unsigned)((ngrp + 7) / 8 * 8));
   const size_t lds = (size_t)g.n0 * kStickTile * sizeof(cplx<T>);
