@@ -93,6 +93,14 @@ struct wtd_ctx {
   // all pairs kept in the tile order of the round-robin contraction
   // (rr_tile_base) rather than row-major
   bool tile_pairs = false;
+  // The all-pairs potentials depend on the orbitals only: an apply that forms
+  // them does so on pair_stream (default priority), forked from the context
+  // stream at the apply's start and joined before the contraction, so the
+  // projection, trial transform and Hartree solve run beside them.
+  hipStream_t pair_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool pairs_pending = false;  // pairs enqueued on pair_stream, not yet joined
+  void* dsth = nullptr;        // density sticks of the Hartree solve ((max_nb + 1) / 2 packs)
   void* wst = nullptr;       // [max packs][n0][nw] complex
   void* dst = nullptr;       // [pair chunk][n0][nd] complex
   void* ag = nullptr;        // [max_nb][nocc][2 npw]
@@ -191,8 +199,14 @@ void* dalloc(wtd_ctx* c, size_t bytes) {
 }
 
 void free_all(wtd_ctx* c) {
+  if (c->pair_stream) (void)hipStreamSynchronize(c->pair_stream);
   for (auto& b : c->bufs) (void)hipFree(b.p);
   c->bufs.clear();
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->pair_stream) (void)hipStreamDestroy(c->pair_stream);
+  c->ev_fork = c->ev_join = nullptr;
+  c->pair_stream = nullptr;
   for (auto e : c->prof.pool) (void)hipEventDestroy(e);
   c->prof.pool.clear();
 }
@@ -697,6 +711,10 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   c->max_pair_chunk = c->pair_chunk;
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
   c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nds * sizeof(cplx<T>));
+  c->dsth = dalloc(c, (size_t)((mnb + 1) / 2) * c->g.n0 * c->g.nds * sizeof(cplx<T>));
+  WTD_HIP(hipStreamCreateWithFlags(&c->pair_stream, hipStreamNonBlocking));
+  WTD_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  WTD_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
   c->rg = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
   c->S = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
@@ -726,6 +744,57 @@ void transform_occ(wtd_ctx* c, const double* c_occ) {
 // mask: the terms to apply (WTD_TERM_*; K2e and K2d only for the full operator).
 // At the Gamma point the trial fields are real, so K2e's density
 // sum_v' conj(a_v') phi_v' equals K1e's and the two add up to one response term.
+// The all-pairs potentials are kept from an earlier apply (pair cache on).
+bool pairs_kept(const wtd_ctx* c) {
+  return c->tau_cache && c->tau_valid && c->tau_il == c->tile_pairs;
+}
+
+// Step 5 for all pairs at once, on stream s: pair potentials in chunks of
+// packed pairs, stored interleaved by groups of kTauIl pairs in the tile order
+// of the round-robin contraction where it reads them (a chunk starts on a
+// whole group, so its groups start at field 2 p0 in either layout).
+template <typename T>
+void form_pairs(wtd_ctx* c, hipStream_t s) {
+  const Geometry& g = c->g;
+  const bool il = c->tile_pairs;
+  WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
+              WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
+  for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
+    const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
+    const int nf = std::min(2 * np, c->npairs - 2 * p0);
+    prof_next(c, 3);
+    launch_pairs_to_dsticks<T>(g, (const T*)c->phi, c->quads + p0, np, c->nocc,
+                               (cplx<T>*)c->dst, s);
+    prof_next(c, 4);
+    launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
+    prof_next(c, 5);
+    launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
+                                (T*)c->tau + (int64_t)2 * p0 * g.nr, s, il);
+  }
+  c->tau_valid = c->tau_cache;
+  c->tau_il = il;
+}
+
+// At the start of an apply: enqueue the all-pairs potentials on pair_stream
+// after the work already on the context stream (they read only the orbital
+// fields), to be joined before the contraction.  Not with stage profiling
+// (its events time one stream) nor with WTD_PAIR_OVERLAP=0.
+template <typename T>
+void fork_pairs(wtd_ctx* c, uint32_t mask) {
+  c->pairs_pending = false;
+  static const bool off = [] {
+    const char* e = std::getenv("WTD_PAIR_OVERLAP");
+    return e && std::atoi(e) == 0;
+  }();
+  const bool k1d = (mask & WTD_TERM_K1D) && c->alpha != 0.0;
+  if (off || !k1d || c->row_block || c->prof.on || pairs_kept(c)) return;
+  WTD_HIP(hipEventRecord(c->ev_fork, c->stream));
+  WTD_HIP(hipStreamWaitEvent(c->pair_stream, c->ev_fork, 0));
+  form_pairs<T>(c, c->pair_stream);
+  WTD_HIP(hipEventRecord(c->ev_join, c->pair_stream));
+  c->pairs_pending = true;
+}
+
 template <typename T>
 void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   const Geometry& g = c->g;
@@ -753,9 +822,9 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   if (k1e) {
     prof_next(c, 2);
     const int nh = (nb + 1) / 2;
-    launch_pairs_to_dsticks<T>(g, (const T*)c->drho, c->hquads, nh, nb, (cplx<T>*)c->dst, s);
-    launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, nh, s);
-    launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, nh, nb, (T*)c->vh, s);
+    launch_pairs_to_dsticks<T>(g, (const T*)c->drho, c->hquads, nh, nb, (cplx<T>*)c->dsth, s);
+    launch_dstick_poisson<T>(g, (cplx<T>*)c->dsth, nh, s);
+    launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dsth, nh, nb, (T*)c->vh, s);
   }
   if (c->row_block) {
     // 5'-6'. R = response term, then the exchange sum block pair by block pair
@@ -798,28 +867,14 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
       }
     }
   }
-  // 5. pair potentials, in chunks of packed pairs; stored interleaved by groups
-  // of kTauIl pairs when the round-robin contraction reads them (a chunk starts
-  // on a whole group, so its groups start at field 2 p0 in either layout)
-  const bool il = c->tile_pairs;
-  if (k1d && !c->row_block && !(c->tau_cache && c->tau_valid && c->tau_il == il)) {
-    WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
-                WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
-    for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
-      const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
-      const int nf = std::min(2 * np, c->npairs - 2 * p0);
-      prof_next(c, 3);
-      launch_pairs_to_dsticks<T>(g, (const T*)c->phi, c->quads + p0, np, c->nocc,
-                                 (cplx<T>*)c->dst, s);
-      prof_next(c, 4);
-      launch_dstick_poisson<T>(g, (cplx<T>*)c->dst, np, s);
-      prof_next(c, 5);
-      launch_dsticks_to_fields<T>(g, (const cplx<T>*)c->dst, np, nf,
-                                  (T*)c->tau + (int64_t)2 * p0 * g.nr, s, il);
-    }
-    c->tau_valid = c->tau_cache;
-    c->tau_il = il;
+  // 5. pair potentials: joined from pair_stream, or formed here
+  if (c->pairs_pending) {
+    WTD_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
+    c->pairs_pending = false;
+  } else if (k1d && !c->row_block && !pairs_kept(c)) {
+    form_pairs<T>(c, s);
   }
+  const bool il = c->tile_pairs;
   // 6. R
   prof_next(c, 6);
   if (c->row_block) {
@@ -904,6 +959,7 @@ void apply_impl(wtd_ctx* c, int nb, const T* a, T* la, uint32_t mask) {
   const int nocc = c->nocc, npw = c->npw, nc = c->nc;
   const int K = 2 * npw, F = nb * nocc;
   prof_mark(c, 0);
+  fork_pairs<T>(c, mask);
   launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s,
                        (T*)c->gemm_scratch, c->gemm_scratch_elems);
   launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
@@ -922,6 +978,7 @@ void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout, ui
   const int nocc = c->nocc, npw = c->npw, nc = c->nc;
   const int K = 2 * npw, F = nb * nocc;
   prof_mark(c, 0);
+  fork_pairs<T>(c, mask);
   if (sizeof(T) == sizeof(double))
     WTD_HIP(hipMemcpyAsync(c->S, X, (size_t)F * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
   else
