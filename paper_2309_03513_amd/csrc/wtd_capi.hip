@@ -97,10 +97,19 @@ struct wtd_ctx {
   // them does so on pair_stream (default priority), forked from the context
   // stream at the apply's start and joined before the contraction, so the
   // projection, trial transform and Hartree solve run beside them.
-  hipStream_t pair_stream = nullptr;
+  // In FP64 the pair chunks themselves are pipelined over two streams and two
+  // stick buffers: chunk k + 1's forward plane pass on pair_stream while chunk
+  // k's stick Poisson and inverse plane pass run on pair_stream2 (FP64 72^3
+  // apply 48.3 -> 46.8 ms; in FP32, where the forward and inverse plane
+  // kernels share the LDS of a CU, 19.64 -> 19.89 ms, so FP32 keeps one pair
+  // stream).
+  hipStream_t pair_stream = nullptr, pair_stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool pairs_pending = false;  // pairs enqueued on pair_stream, not yet joined
+  hipEvent_t ev_fwd[2] = {}, ev_free[2] = {};
+  bool pairs_pending = false;  // pairs enqueued on the pair streams, not yet joined
+  int last_fwd = 0;            // ev_fwd slot recorded last on pair_stream
   void* dsth = nullptr;        // density sticks of the Hartree solve ((max_nb + 1) / 2 packs)
+  void* dst2 = nullptr;        // second stick buffer of the pipelined pair chunks
   void* wst = nullptr;       // [max packs][n0][nw] complex
   void* dst = nullptr;       // [pair chunk][n0][nd] complex
   void* ag = nullptr;        // [max_nb][nocc][2 npw]
@@ -202,11 +211,15 @@ void free_all(wtd_ctx* c) {
   if (c->pair_stream) (void)hipStreamSynchronize(c->pair_stream);
   for (auto& b : c->bufs) (void)hipFree(b.p);
   c->bufs.clear();
-  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->pair_stream2) (void)hipStreamSynchronize(c->pair_stream2);
+  for (hipEvent_t* e : {&c->ev_fork, &c->ev_join, &c->ev_fwd[0], &c->ev_fwd[1], &c->ev_free[0],
+                        &c->ev_free[1]}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
   if (c->pair_stream) (void)hipStreamDestroy(c->pair_stream);
-  c->ev_fork = c->ev_join = nullptr;
-  c->pair_stream = nullptr;
+  if (c->pair_stream2) (void)hipStreamDestroy(c->pair_stream2);
+  c->pair_stream = c->pair_stream2 = nullptr;
   for (auto e : c->prof.pool) (void)hipEventDestroy(e);
   c->prof.pool.clear();
 }
@@ -712,9 +725,13 @@ void create_impl(wtd_ctx* c, const wtd_system* sys) {
   const int dchunk = std::max(c->pair_chunk, (mnb + 1) / 2);
   c->dst = dalloc(c, (size_t)dchunk * c->g.n0 * c->g.nds * sizeof(cplx<T>));
   c->dsth = dalloc(c, (size_t)((mnb + 1) / 2) * c->g.n0 * c->g.nds * sizeof(cplx<T>));
+  if (!c->row_block && sizeof(T) == 8)
+    c->dst2 = dalloc(c, (size_t)c->pair_chunk * c->g.n0 * c->g.nds * sizeof(cplx<T>));
   WTD_HIP(hipStreamCreateWithFlags(&c->pair_stream, hipStreamNonBlocking));
-  WTD_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-  WTD_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  WTD_HIP(hipStreamCreateWithFlags(&c->pair_stream2, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&c->ev_fork, &c->ev_join, &c->ev_fwd[0], &c->ev_fwd[1], &c->ev_free[0],
+                        &c->ev_free[1]})
+    WTD_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   c->ag = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
   c->rg = dalloc(c, (size_t)mnb * nocc * K * sizeof(T));
   c->S = dalloc(c, (size_t)mnb * nocc * nc * sizeof(T));
@@ -775,10 +792,38 @@ void form_pairs(wtd_ctx* c, hipStream_t s) {
   c->tau_il = il;
 }
 
-// At the start of an apply: enqueue the all-pairs potentials on pair_stream
-// after the work already on the context stream (they read only the orbital
-// fields), to be joined before the contraction.  Not with stage profiling
-// (its events time one stream) nor with WTD_PAIR_OVERLAP=0.
+// The same pipelined over the two pair streams and the two stick buffers
+// (events order each buffer's reuse after the inverse pass that read it).
+template <typename T>
+void form_pairs_pipelined(wtd_ctx* c) {
+  const Geometry& g = c->g;
+  const bool il = c->tile_pairs;
+  WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
+              WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
+  hipStream_t sf = c->pair_stream, sp = c->pair_stream2;
+  cplx<T>* buf[2] = {(cplx<T>*)c->dst, (cplx<T>*)c->dst2};
+  int k = 0;
+  for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk, ++k) {
+    const int b = k & 1;
+    const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
+    const int nf = std::min(2 * np, c->npairs - 2 * p0);
+    if (k >= 2) WTD_HIP(hipStreamWaitEvent(sf, c->ev_free[b], 0));
+    launch_pairs_to_dsticks<T>(g, (const T*)c->phi, c->quads + p0, np, c->nocc, buf[b], sf);
+    WTD_HIP(hipEventRecord(c->ev_fwd[b], sf));
+    WTD_HIP(hipStreamWaitEvent(sp, c->ev_fwd[b], 0));
+    launch_dstick_poisson<T>(g, buf[b], np, sp);
+    launch_dsticks_to_fields<T>(g, buf[b], np, nf, (T*)c->tau + (int64_t)2 * p0 * g.nr, sp, il);
+    WTD_HIP(hipEventRecord(c->ev_free[b], sp));
+    c->last_fwd = b;
+  }
+  c->tau_valid = c->tau_cache;
+  c->tau_il = il;
+}
+
+// At the start of an apply: enqueue the all-pairs potentials on the pair
+// streams after the work already on the context stream (they read only the
+// orbital fields), to be joined before the contraction.  Not with stage
+// profiling (its events time one stream) nor with WTD_PAIR_OVERLAP=0.
 template <typename T>
 void fork_pairs(wtd_ctx* c, uint32_t mask) {
   c->pairs_pending = false;
@@ -788,10 +833,22 @@ void fork_pairs(wtd_ctx* c, uint32_t mask) {
   }();
   const bool k1d = (mask & WTD_TERM_K1D) && c->alpha != 0.0;
   if (off || !k1d || c->row_block || c->prof.on || pairs_kept(c)) return;
+  // under stream capture the chunks stay on one pair stream: the two-stream
+  // pipeline (events re-recorded and waited on across both forked streams)
+  // crashed the capture's end, which the one-stream form does not
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  WTD_HIP(hipStreamIsCapturing(c->stream, &cap));
   WTD_HIP(hipEventRecord(c->ev_fork, c->stream));
   WTD_HIP(hipStreamWaitEvent(c->pair_stream, c->ev_fork, 0));
-  form_pairs<T>(c, c->pair_stream);
-  WTD_HIP(hipEventRecord(c->ev_join, c->pair_stream));
+  if (c->dst2 && cap == hipStreamCaptureStatusNone) {
+    WTD_HIP(hipStreamWaitEvent(c->pair_stream2, c->ev_fork, 0));
+    form_pairs_pipelined<T>(c);
+    WTD_HIP(hipEventRecord(c->ev_join, c->pair_stream2));
+  } else {
+    form_pairs<T>(c, c->pair_stream);
+    WTD_HIP(hipEventRecord(c->ev_join, c->pair_stream));
+    c->last_fwd = -1;
+  }
   c->pairs_pending = true;
 }
 
@@ -869,6 +926,8 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   }
   // 5. pair potentials: joined from pair_stream, or formed here
   if (c->pairs_pending) {
+    // the pair streams end in the context stream
+    if (c->last_fwd >= 0) WTD_HIP(hipStreamWaitEvent(s, c->ev_fwd[c->last_fwd], 0));
     WTD_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
     c->pairs_pending = false;
   } else if (k1d && !c->row_block && !pairs_kept(c)) {
