@@ -898,6 +898,9 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
 // other, keeps the first plane in registers and writes the four values of a
 // point as one vector (16 bytes in FP32), so every store of a wave covers whole
 // lines; the second pack's first stick rounds load during the first transform.
+// The stores carry the streaming hint: the pair potentials are read back only by
+// the contraction, after every chunk (at 72^3 the stick Poisson of the chunks
+// measured 3.19 -> 3.14 ms per apply with it, the apply 19.43 -> 19.35 ms).
 template <int MB1, int MB2, int SN, typename T>
 __global__ void __launch_bounds__(kPlaneThreads)
 k_dsticks_to_groups(const cplx<T>* __restrict__ dst, int npack, int nfield, int n0, int n1,
@@ -972,7 +975,8 @@ k_dsticks_to_groups(const cplx<T>* __restrict__ dst, int npack, int nfield, int 
     if (PL % kPlaneThreads == 0 || i < PL) {
       const cplx<T> b = two ? pl[i] : cplx<T>{T(0), T(0)};
       if (full) {
-        *reinterpret_cast<v4*>(o + 4 * (int64_t)i) = v4{keep[e].x, keep[e].y, b.x, b.y};
+        __builtin_nontemporal_store(v4{keep[e].x, keep[e].y, b.x, b.y},
+                                     reinterpret_cast<v4*>(o + 4 * (int64_t)i));
       } else {
         o[4 * (int64_t)i] = keep[e].x;
         if (f0 + 1 < nfield) o[4 * (int64_t)i + 1] = keep[e].y;
