@@ -34,10 +34,10 @@ METRIC = "Liouville trial-vector applies/s, 72³ grid Nocc=128; FP32 vs FP64 at 
 # for the kernel sources they were taken on (profiles/liouville_c2_fp32_hbm_counters.md).
 MEASURED_TRAFFIC = {
     "pair_plane_fwd": {
-        "bytes": 736.8e6,
+        "bytes": 737.0e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "d39815df3c6187845926d0a9b645b95a71df9456d5c78a6ac4268123f0d41738",
+                "2f5a9a4a8dc9e1c9cccb28356729b3cf5ad15955a4f2b754699345aa5b734b03",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -49,10 +49,10 @@ MEASURED_TRAFFIC = {
         },
     },
     "pair_stick_poisson": {
-        "bytes": 1295.5e6,
+        "bytes": 1295.6e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "d39815df3c6187845926d0a9b645b95a71df9456d5c78a6ac4268123f0d41738",
+                "2f5a9a4a8dc9e1c9cccb28356729b3cf5ad15955a4f2b754699345aa5b734b03",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -67,7 +67,7 @@ MEASURED_TRAFFIC = {
         "bytes": 1983.1e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_transforms.hip":
-                "d39815df3c6187845926d0a9b645b95a71df9456d5c78a6ac4268123f0d41738",
+                "2f5a9a4a8dc9e1c9cccb28356729b3cf5ad15955a4f2b754699345aa5b734b03",
             "paper_2309_03513_amd/csrc/wtd_fft_ct.h":
                 "53a2da7c45b4a87809c48d568ecb5c71ac2ffdf9f45ad20bb25e01c6e8d8c088",
             "paper_2309_03513_amd/csrc/wtd_fft.h":
@@ -79,7 +79,7 @@ MEASURED_TRAFFIC = {
         },
     },
     "contract": {
-        "bytes": 18700.4e6,
+        "bytes": 18700.8e6,
         "sources": {
             "paper_2309_03513_amd/csrc/wtd_contract.hip":
                 "81c44a0afcc642c54db489c3ac2b1557a0a71aac173915aa769fd70828fc8c3a",

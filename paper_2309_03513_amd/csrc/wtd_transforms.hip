@@ -48,6 +48,16 @@ constexpr int pair_items() {
   return (SN > 0 && SN * SN <= 72 * 72 && sizeof(T) == 8) ? kPairItems : 1;
 }
 
+// items per workgroup of the inverse group kernel: FP64 planes take one
+// workgroup per CU, whose next item's loads are then hidden by prefetch (72^3
+// FP64 inverse pass 13.3 ms per apply with one item, 12.1 with 2, 11.5 with 4);
+// FP32 keeps one item and three workgroups per CU (6.5 ms against 4.5 with 2)
+constexpr int kGroupItems = 4;
+template <typename T>
+constexpr int group_items() {
+  return sizeof(T) == 8 ? kGroupItems : 1;
+}
+
 int min_radix(const FFTPlan& p) {
   int r = 8;
   for (int i = 0; i < p.np; ++i) r = p.rad[i] < r ? p.rad[i] : r;
@@ -893,11 +903,13 @@ k_dsticks_to_fields(const cplx<T>* __restrict__ dst, int npack, int il, int nfie
 }
 
 // Density sticks -> pair potentials in the 4-pair interleaved layout, for
-// compile-time planes: the workgroup of item (plane i0, group q) transforms
-// packs 2q and 2q + 1 (the four fields of interleave group q) one after the
-// other, keeps the first plane in registers and writes the four values of a
-// point as one vector (16 bytes in FP32), so every store of a wave covers whole
-// lines; the second pack's first stick rounds load during the first transform.
+// compile-time planes: item (plane i0, group q) transforms packs 2q and 2q + 1
+// (the four fields of interleave group q) one after the other, keeps the first
+// plane in registers and writes the four values of a point as one vector (16
+// bytes in FP32), so every store of a wave covers whole lines; the second
+// pack's first stick rounds load during the first transform.  A workgroup takes
+// group_items() consecutive items; with more than one, the next item's first
+// stick rounds load during the current item's second transform and stores.
 // The stores carry the streaming hint: the pair potentials are read back only by
 // the contraction, after every chunk (at 72^3 the stick Poisson of the chunks
 // measured 3.19 -> 3.14 ms per apply with it, the apply 19.43 -> 19.35 ms).
@@ -913,75 +925,157 @@ k_dsticks_to_groups(const cplx<T>* __restrict__ dst, int npack, int nfield, int 
   constexpr int PL = SN * SN;
   constexpr int EL = (PL + kPlaneThreads - 1) / kPlaneThreads;
   constexpr int KR = stick_regs<SN>();
+  constexpr int NI = group_items<T>();
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* twl = pl + PL;
-  const int ngrp = (npack + 1) / 2;
-  const int item = xcd_item(n0 * ngrp);
-  if (item < 0) return;
-  stage_twiddles<SN>(twl, tw1);
-  const int i0 = item / ngrp;
-  const int q = item - i0 * ngrp;
-  const int64_t nr = (int64_t)n0 * PL;
-  const bool two = 2 * q + 1 < npack;
-  int kp[KR];
-  cplx<T> sv[KR];
-  auto load = [&](int pack) {
-    const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+  if constexpr (NI == 1) {
+    // (the one-item form on its own: written as the loop below with one
+    // item it took 106 VGPRs instead of 79, two FP32 workgroups per CU
+    // instead of three)
+    const int ngrp = (npack + 1) / 2;
+    const int item = xcd_item(n0 * ngrp);
+    if (item < 0) return;
+    stage_twiddles<SN>(twl, tw1);
+    const int i0 = item / ngrp;
+    const int q = item - i0 * ngrp;
+    const int64_t nr = (int64_t)n0 * PL;
+    const bool two = 2 * q + 1 < npack;
+    int kp[KR];
+    cplx<T> sv[KR];
+    auto load = [&](int pack) {
+      const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+#pragma unroll
+      for (int e = 0; e < KR; ++e) {
+        const int st = threadIdx.x + e * kPlaneThreads;
+        sv[e] = kp[e] >= 0 ? src[st] : cplx<T>{T(0), T(0)};
+      }
+    };
+    // fill the plane with pack `pack` (registers sv for the first rounds)
+    auto fill = [&](int pack) {
+      for (int i = threadIdx.x; i < PL; i += blockDim.x) pl[i] = {T(0), T(0)};
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < KR; ++e)
+        if (kp[e] >= 0) pl[kp[e]] = sv[e];
+      const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+      for (int st = threadIdx.x + KR * kPlaneThreads; st < nd; st += blockDim.x)
+        pl[k12[st]] = src[st];
+      __syncthreads();
+    };
 #pragma unroll
     for (int e = 0; e < KR; ++e) {
       const int st = threadIdx.x + e * kPlaneThreads;
-      sv[e] = kp[e] >= 0 ? src[st] : cplx<T>{T(0), T(0)};
+      kp[e] = st < nd ? k12[st] : -1;
     }
-  };
-  // fill the plane with pack `pack` (registers sv for the first rounds)
-  auto fill = [&](int pack) {
-    for (int i = threadIdx.x; i < PL; i += blockDim.x) pl[i] = {T(0), T(0)};
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < KR; ++e)
-      if (kp[e] >= 0) pl[kp[e]] = sv[e];
-    const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
-    for (int st = threadIdx.x + KR * kPlaneThreads; st < nd; st += blockDim.x)
-      pl[k12[st]] = src[st];
-    __syncthreads();
-  };
-#pragma unroll
-  for (int e = 0; e < KR; ++e) {
-    const int st = threadIdx.x + e * kPlaneThreads;
-    kp[e] = st < nd ? k12[st] : -1;
-  }
-  load(2 * q);
-  fill(2 * q);
-  if (two) load(2 * q + 1);
-  plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  cplx<T> keep[EL];
-#pragma unroll
-  for (int e = 0; e < EL; ++e) {
-    const int i = threadIdx.x + e * kPlaneThreads;
-    if (PL % kPlaneThreads == 0 || i < PL) keep[e] = pl[i];
-  }
-  __syncthreads();
-  if (two) {
-    fill(2 * q + 1);
+    load(2 * q);
+    fill(2 * q);
+    if (two) load(2 * q + 1);
     plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
-  }
-  // group q holds fields 4q .. 4q + 3 (those below nfield exist)
-  T* o = out + ((int64_t)q * nr + (int64_t)i0 * PL) * 4;
-  const int f0 = 4 * q;
-  const bool full = f0 + 3 < nfield;
+    cplx<T> keep[EL];
 #pragma unroll
-  for (int e = 0; e < EL; ++e) {
-    const int i = threadIdx.x + e * kPlaneThreads;
-    if (PL % kPlaneThreads == 0 || i < PL) {
-      const cplx<T> b = two ? pl[i] : cplx<T>{T(0), T(0)};
-      if (full) {
-        __builtin_nontemporal_store(v4{keep[e].x, keep[e].y, b.x, b.y},
-                                     reinterpret_cast<v4*>(o + 4 * (int64_t)i));
-      } else {
-        o[4 * (int64_t)i] = keep[e].x;
-        if (f0 + 1 < nfield) o[4 * (int64_t)i + 1] = keep[e].y;
-        if (f0 + 2 < nfield) o[4 * (int64_t)i + 2] = b.x;
+    for (int e = 0; e < EL; ++e) {
+      const int i = threadIdx.x + e * kPlaneThreads;
+      if (PL % kPlaneThreads == 0 || i < PL) keep[e] = pl[i];
+    }
+    __syncthreads();
+    if (two) {
+      fill(2 * q + 1);
+      plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+    }
+    // group q holds fields 4q .. 4q + 3 (those below nfield exist)
+    T* o = out + ((int64_t)q * nr + (int64_t)i0 * PL) * 4;
+    const int f0 = 4 * q;
+    const bool full = f0 + 3 < nfield;
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+      const int i = threadIdx.x + e * kPlaneThreads;
+      if (PL % kPlaneThreads == 0 || i < PL) {
+        const cplx<T> b = two ? pl[i] : cplx<T>{T(0), T(0)};
+        if (full) {
+          __builtin_nontemporal_store(v4{keep[e].x, keep[e].y, b.x, b.y},
+                                       reinterpret_cast<v4*>(o + 4 * (int64_t)i));
+        } else {
+          o[4 * (int64_t)i] = keep[e].x;
+          if (f0 + 1 < nfield) o[4 * (int64_t)i + 1] = keep[e].y;
+          if (f0 + 2 < nfield) o[4 * (int64_t)i + 2] = b.x;
+        }
       }
+    }
+  } else {
+    const int ngrp = (npack + 1) / 2;
+    const int total = n0 * ngrp;
+    const int wg = xcd_item((total + NI - 1) / NI);
+    if (wg < 0) return;
+    stage_twiddles<SN>(twl, tw1);
+    const int it0 = wg * NI, it1 = min(total, it0 + NI);
+    const int64_t nr = (int64_t)n0 * PL;
+    int kp[KR];
+    cplx<T> sv[KR];
+    auto load = [&](int pack, int i0) {
+      const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+#pragma unroll
+      for (int e = 0; e < KR; ++e) {
+        const int st = threadIdx.x + e * kPlaneThreads;
+        sv[e] = kp[e] >= 0 ? src[st] : cplx<T>{T(0), T(0)};
+      }
+    };
+    // fill the plane with pack `pack` (registers sv for the first rounds)
+    auto fill = [&](int pack, int i0) {
+      for (int i = threadIdx.x; i < PL; i += blockDim.x) pl[i] = {T(0), T(0)};
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < KR; ++e)
+        if (kp[e] >= 0) pl[kp[e]] = sv[e];
+      const cplx<T>* src = dst + ((int64_t)pack * n0 + i0) * nds;
+      for (int st = threadIdx.x + KR * kPlaneThreads; st < nd; st += blockDim.x)
+        pl[k12[st]] = src[st];
+      __syncthreads();
+    };
+#pragma unroll
+    for (int e = 0; e < KR; ++e) {
+      const int st = threadIdx.x + e * kPlaneThreads;
+      kp[e] = st < nd ? k12[st] : -1;
+    }
+    load(2 * (it0 % ngrp), it0 / ngrp);
+    for (int item = it0; item < it1; ++item) {
+      const bool next = item + 1 < it1;
+      const int i0 = item / ngrp;
+      const int q = item - i0 * ngrp;
+      const bool two = 2 * q + 1 < npack;
+      fill(2 * q, i0);
+      if (two) load(2 * q + 1, i0);
+      plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+      cplx<T> keep[EL];
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) keep[e] = pl[i];
+      }
+      __syncthreads();
+      if (two) fill(2 * q + 1, i0);
+      if (next) load(2 * ((item + 1) % ngrp), (item + 1) / ngrp);
+      if (two) plane_fft<+1, SN, MB1, MB2>(pl, P1, P2, n1, n2, tw1, tw2, twl);
+      // group q holds fields 4q .. 4q + 3 (those below nfield exist)
+      T* o = out + ((int64_t)q * nr + (int64_t)i0 * PL) * 4;
+      const int f0 = 4 * q;
+      const bool full = f0 + 3 < nfield;
+#pragma unroll
+      for (int e = 0; e < EL; ++e) {
+        const int i = threadIdx.x + e * kPlaneThreads;
+        if (PL % kPlaneThreads == 0 || i < PL) {
+          const cplx<T> b = two ? pl[i] : cplx<T>{T(0), T(0)};
+          if (full) {
+            __builtin_nontemporal_store(v4{keep[e].x, keep[e].y, b.x, b.y},
+                                         reinterpret_cast<v4*>(o + 4 * (int64_t)i));
+          } else {
+            o[4 * (int64_t)i] = keep[e].x;
+            if (f0 + 1 < nfield) o[4 * (int64_t)i + 1] = keep[e].y;
+            if (f0 + 2 < nfield) o[4 * (int64_t)i + 2] = b.x;
+          }
+        }
+      }
+      // (the next item's fill clears the plane these stores read)
+      if (next) __syncthreads();
     }
   }
 }
@@ -1571,7 +1665,8 @@ void launch_dsticks_to_fields(const Geometry& g, const cplx<T>* dst, int npack, 
   // VGPRs, one workgroup per CU where the LDS holds two)
   if (il && plane_static(g) > 0 && plane_static(g) != 96) {
     const int ngrp = (npack + 1) / 2;
-    dim3 grid((unsigned)((g.n0 * ngrp + 7) / 8 * 8));
+    const int wgs = (g.n0 * ngrp + group_items<T>() - 1) / group_items<T>();
+    dim3 grid((unsigned)((wgs + 7) / 8 * 8));
     const size_t lds = (size_t)g.plane * sizeof(cplx<T>);
     WTD_PLANE_LAUNCH_STATIC(k_dsticks_to_groups, T, grid, lds, s, dst, npack, nfield, g.n0, g.n1,
                             g.n2, g.nd, g.nds, g.dst_k12, g.plan1d, g.plan2,
