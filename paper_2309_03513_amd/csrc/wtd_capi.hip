@@ -820,13 +820,35 @@ void form_pairs_pipelined(wtd_ctx* c) {
   c->tau_il = il;
 }
 
+// The context stream waits for the pair work forked by fork_pairs (both pair
+// streams end in it).
+void join_pairs(wtd_ctx* c) {
+  if (!c->pairs_pending) return;
+  if (c->last_fwd >= 0) WTD_HIP(hipStreamWaitEvent(c->stream, c->ev_fwd[c->last_fwd], 0));
+  WTD_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  c->pairs_pending = false;
+}
+
+// Joins the forked pair work when an apply stops with an error between its
+// fork and its join (the normal path joins before the contraction), so that no
+// later work on the context stream overlaps it.
+struct PairJoinOnError {
+  wtd_ctx* c;
+  ~PairJoinOnError() {
+    try {
+      join_pairs(c);
+    } catch (...) {
+      // (the error that unwound the apply is the one reported)
+    }
+  }
+};
+
 // At the start of an apply: enqueue the all-pairs potentials on the pair
 // streams after the work already on the context stream (they read only the
 // orbital fields), to be joined before the contraction.  Not with stage
 // profiling (its events time one stream) nor with WTD_PAIR_OVERLAP=0.
 template <typename T>
 void fork_pairs(wtd_ctx* c, uint32_t mask) {
-  c->pairs_pending = false;
   static const bool off = [] {
     const char* e = std::getenv("WTD_PAIR_OVERLAP");
     return e && std::atoi(e) == 0;
@@ -926,10 +948,7 @@ void apply_core(wtd_ctx* c, int nb, uint32_t mask) {
   }
   // 5. pair potentials: joined from pair_stream, or formed here
   if (c->pairs_pending) {
-    // the pair streams end in the context stream
-    if (c->last_fwd >= 0) WTD_HIP(hipStreamWaitEvent(s, c->ev_fwd[c->last_fwd], 0));
-    WTD_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
-    c->pairs_pending = false;
+    join_pairs(c);
   } else if (k1d && !c->row_block && !pairs_kept(c)) {
     form_pairs<T>(c, s);
   }
@@ -1019,6 +1038,7 @@ void apply_impl(wtd_ctx* c, int nb, const T* a, T* la, uint32_t mask) {
   const int K = 2 * npw, F = nb * nocc;
   prof_mark(c, 0);
   fork_pairs<T>(c, mask);
+  PairJoinOnError join_on_error{c};
   launch_gemm<T, true>(F, nc, K, a, K, (const T*)c->c_condw, K, (T*)c->S, nc, s,
                        (T*)c->gemm_scratch, c->gemm_scratch_elems);
   launch_gemm<T, false>(F, K, nc, (const T*)c->S, nc, (const T*)c->c_cond, K, (T*)c->ag, K, s);
@@ -1038,6 +1058,7 @@ void apply_transition_impl(wtd_ctx* c, int nb, const double* X, double* Tout, ui
   const int K = 2 * npw, F = nb * nocc;
   prof_mark(c, 0);
   fork_pairs<T>(c, mask);
+  PairJoinOnError join_on_error{c};
   if (sizeof(T) == sizeof(double))
     WTD_HIP(hipMemcpyAsync(c->S, X, (size_t)F * nc * sizeof(double), hipMemcpyDeviceToDevice, s));
   else
