@@ -30,8 +30,11 @@
  * returns a thread-local message for the last failure.  No exception crosses
  * the ABI.  One context is not thread-safe; distinct contexts are independent.
  * Device pointers are HIP device memory on the device that was current when
- * the context was created; every device operation is enqueued on the HIP
- * stream given at creation.
+ * the context was created; every device operation is ordered on the HIP
+ * stream given at creation.  An apply may run its pair potentials on streams
+ * of the context's own, forked from that stream after the work already on it
+ * and joined back into it before the apply's later stages, so the apply is
+ * one stretch of that stream to the caller and to a graph captured on it.
  */
 #ifndef WTD_H
 #define WTD_H

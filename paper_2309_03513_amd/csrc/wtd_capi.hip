@@ -775,7 +775,7 @@ void form_pairs(wtd_ctx* c, hipStream_t s) {
   const Geometry& g = c->g;
   const bool il = c->tile_pairs;
   WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
-              WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
+              WTD_ERR_SHAPE, "pair chunk must be a multiple of 2 packs (whole groups of 4 pairs)");
   for (int p0 = 0; p0 < c->npack_pairs; p0 += c->pair_chunk) {
     const int np = std::min(c->pair_chunk, c->npack_pairs - p0);
     const int nf = std::min(2 * np, c->npairs - 2 * p0);
@@ -799,7 +799,7 @@ void form_pairs_pipelined(wtd_ctx* c) {
   const Geometry& g = c->g;
   const bool il = c->tile_pairs;
   WTD_REQUIRE(!il || (2 * c->pair_chunk) % kTauIl == 0 || c->pair_chunk >= c->npack_pairs,
-              WTD_ERR_SHAPE, "pair chunk must be a multiple of 4 packs");
+              WTD_ERR_SHAPE, "pair chunk must be a multiple of 2 packs (whole groups of 4 pairs)");
   hipStream_t sf = c->pair_stream, sp = c->pair_stream2;
   cplx<T>* buf[2] = {(cplx<T>*)c->dst, (cplx<T>*)c->dst2};
   int k = 0;
