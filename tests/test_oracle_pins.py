@@ -232,6 +232,46 @@ def test_davidson_restart_path(systems):
     assert np.abs(th - ev[:3]).max() <= 1e-10
 
 
+def test_rayleigh_ritz_certificate_against_eigh():
+    """The Rayleigh-Ritz certificate on a dense symmetric matrix with a known
+    spectrum: Ritz values equal eigvalsh of the projected matrix, and the
+    Weinstein and Kato-Temple bounds hold, and are tight enough to matter, for
+    perturbed eigenvectors."""
+    from tests.certify import rayleigh_ritz
+    rng = np.random.default_rng(41)
+    n, k = 40, 6
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = 0.1 + 0.1 * np.arange(n) + rng.uniform(-0.02, 0.02, n)
+    A = (Q * ev) @ Q.T
+    A = 0.5 * (A + A.T)
+    V = Q[:, :k] + 1e-3 * rng.standard_normal((n, k))
+    theta, Y, rn, kt = rayleigh_ritz(lambda B: A @ B, V)
+    P, _ = np.linalg.qr(V)
+    assert np.abs(theta - np.linalg.eigvalsh(P.T @ A @ P)).max() <= 1e-13
+    assert np.abs(Y.T @ Y - np.eye(k)).max() <= 1e-13
+    err = np.abs(theta - ev[:k])
+    assert np.all(err <= rn + 1e-14)
+    assert all(err[i] <= kt[i] + 1e-14 for i in range(k - 1)) and kt[-1] is None
+    # the perturbation is visible and the quadratic bound is well below the linear one
+    assert err.max() > 1e-8 and all(kt[i] < 0.2 * rn[i] for i in range(k - 1))
+
+
+def test_rayleigh_ritz_on_oracle_operator_bounds_the_dense_roots(systems):
+    """The certificate with the oracle's operator as the matvec (as the GPU
+    eigenvector checks use it) on perturbed eigenvectors of C1's dense matrix."""
+    from tests.certify import rayleigh_ritz, transition_matvec
+    s = systems("c1")
+    ev, W = np.linalg.eigh(_dense(s))
+    rng = np.random.default_rng(43)
+    k = 5
+    V = W[:, :k] + 1e-4 * rng.standard_normal((W.shape[0], k))
+    theta, _, rn, kt = rayleigh_ritz(transition_matvec(s), V)
+    err = np.abs(theta - ev[:k])
+    assert np.all(err <= rn + 1e-13)
+    assert all(err[i] <= kt[i] + 1e-13 for i in range(k - 1))
+    assert all(kt[i] < 0.5 * rn[i] for i in range(k - 1))
+
+
 def test_davidson_exhausted_basis_reports_its_iteration():
     """With a tolerance below rounding, the basis of a 12 x 12 problem fills up
     after three blocks of 4; every later correction is dropped, so the run
