@@ -330,6 +330,22 @@ def accuracy_fp32(s, nb, nroots):
             "reference": "oracle FP64 block Davidson, tests/golden/roots_c2.json"}
 
 
+def kato_temple(theta, rnorm):
+    """Kato-Temple bounds rnorm_i^2 / gap_i of Ritz values theta (ascending) with
+    residual norms rnorm: gap_i is the distance from theta_i to the Weinstein
+    intervals [theta_j - rnorm_j, theta_j + rnorm_j] of its neighbours (none
+    below the lowest root); the highest root has no known upper neighbour (None)."""
+    th, rn = np.asarray(theta, dtype=np.float64), np.asarray(rnorm, dtype=np.float64)
+    out = []
+    for i in range(th.size - 1):
+        below = th[i] - (th[i - 1] + rn[i - 1]) if i > 0 else np.inf
+        above = (th[i + 1] - rn[i + 1]) - th[i]
+        gap = min(below, above)
+        out.append(float(rn[i] ** 2 / gap) if gap > 0 else float("inf"))
+    out.append(None)
+    return out
+
+
 def roots_fp32_vs_fp64(cfg, nb64):
     """Davidson roots of one system in FP32 bulk (block of cfg.nb) and in FP64
     (block of nb64; the 108^3 / Nocc = 432 FP64 context holds 16 trial fields
@@ -350,11 +366,16 @@ def roots_fp32_vs_fp64(cfg, nb64):
         roots[prec] = np.asarray(om)
         out[prec] = {"block": nb, "tol": tol, "iterations": int(nit), "seconds": t,
                      "status": int(st), "max_residual": float(np.max(res)),
-                     "roots_hartree": [float(x) for x in om]}
+                     "roots_hartree": [float(x) for x in om],
+                     "residual_norms": [float(x) for x in res],
+                     "kato_temple_bound_hartree": kato_temple(om, res)}
         log(f"{cfg.name} {prec} davidson: nb={nb}, {nit} iterations, {t:.1f} s, status {st}")
     d = np.abs(roots["fp32"] - roots["fp64"]) / MEV
     out["max_abs_domega_meV"] = float(d.max())
     log(f"{cfg.name}: FP32 roots vs FP64 roots: max |d omega| = {d.max():.4f} meV")
+    kt = [b for b in out["fp64"]["kato_temple_bound_hartree"] if b is not None]
+    log(f"{cfg.name}: FP64 roots within {max(kt):.2e} Ha of the FP64 operator's eigenvalues "
+        f"(Kato-Temple, all but the highest root)")
     return out
 
 
