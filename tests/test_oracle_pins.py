@@ -256,6 +256,22 @@ def test_rayleigh_ritz_certificate_against_eigh():
     assert err.max() > 1e-8 and all(kt[i] < 0.2 * rn[i] for i in range(k - 1))
 
 
+def test_benchmark_kato_temple_matches_certificate():
+    """The benchmark's Kato-Temple bounds of Davidson roots (from Ritz values and
+    residual norms alone) equal the certificate's on the same Ritz pairs."""
+    import bench
+    from tests.certify import rayleigh_ritz
+    rng = np.random.default_rng(47)
+    n, k = 30, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * (0.1 + 0.1 * np.arange(n))) @ Q.T
+    A = 0.5 * (A + A.T)
+    theta, _, rn, kt = rayleigh_ritz(lambda B: A @ B, Q[:, :k] + 1e-3 * rng.standard_normal((n, k)))
+    got = bench.kato_temple(theta, rn)
+    assert got[-1] is None and kt[-1] is None
+    assert np.allclose(got[:-1], kt[:-1], rtol=1e-14, atol=0.0)
+
+
 def test_rayleigh_ritz_on_oracle_operator_bounds_the_dense_roots(systems):
     """The certificate with the oracle's operator as the matvec (as the GPU
     eigenvector checks use it) on perturbed eigenvectors of C1's dense matrix."""
